@@ -1,0 +1,225 @@
+/*
+ * morph.h -- C interface of the MI355X (gfx950) binary morphology library.
+ *
+ * Operations: erosion, dilation, opening and closing of binary images by
+ * rectangular structuring elements, on packed 1-bit bitmaps and on
+ * run-length images, plus conversion between the two (Breuel, "Efficient
+ * Binary and Run Length Morphology and its Application to Document Image
+ * Processing": sections "Run Length Image Coding", "Within-Line
+ * Morphological Operations", "Between Line Boolean Operations", "Efficient
+ * Binary Decompositions", "2D Morphological Operators for Rectangular
+ * Masks", "Conversion Between Image Formats").
+ *
+ * ----------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ *
+ *  Pixels.  An image has `width` x `height` pixels; row 0 is the first row in
+ *  memory; 1 = black = foreground ("in a run").
+ *
+ *  Structuring element.  morph_se_t {w, h, cx, cy} is the rectangle
+ *      B = { (dx,dy) : -cx <= dx <= w-1-cx,  -cy <= dy <= h-1-cy }
+ *  with w, h >= 1, 0 <= cx < w, 0 <= cy < h.  The usual centred origin is
+ *  (w/2, h/2) rounded down.
+ *
+ *  Borders.  Erosion treats pixels outside the image as 1, dilation as 0:
+ *      erode (x,y) = AND of A over [x-cx, x+w-1-cx] x [y-cy, y+h-1-cy]
+ *      dilate(x,y) = OR  of A over [x-(w-1-cx), x+cx] x [y-(h-1-cy), y+cy]
+ *  (dilation uses the reflected window: it is the union of B placed at every
+ *  black pixel).  open = dilate(erode(A)), close = erode(dilate(A)) with the
+ *  same B; each step applies its own outside value to an intermediate that
+ *  exists on the image only.
+ *
+ *  Packed bitmaps (morph_bitmap_t).  Rows of uint64 words; pixel x of row y
+ *  is bit (x & 63) of words[y*stride_words + (x >> 6)] (least significant bit
+ *  first).  stride_words >= ceil(width/64).  Pad bits (x >= width) and pad
+ *  words are ignored on input; on output every bit of word columns
+ *  0 .. ceil(width/64)-1 is written, pad bits as 0; words past that in a row
+ *  are not touched.  `npages` equal-size pages may be stacked: page p
+ *  starts at words + p*height*stride_words and every page is processed on
+ *  its own (its own borders).
+ *
+ *  Run-length images (morph_rle_t).  Row r (r = 0 .. npages*height-1, pages
+ *  stacked) holds the runs row_ptr[r] .. row_ptr[r+1]-1; run k is the
+ *  half-open interval [runs[2k], runs[2k+1]) of black pixels.  Runs of a row
+ *  are ascending, non-empty and separated by at least one white pixel
+ *  (end_k < start_{k+1}), which makes the form unique.  Inputs must be in
+ *  this form; outputs always are.  `capacity` is the number of runs the
+ *  runs array can hold (2*capacity int32).  An output's true run count is
+ *  always written to row_ptr[npages*height]; if it exceeds capacity the
+ *  runs past capacity are not written and the result is incomplete (check
+ *  after the stream has finished; morph_rle_max_runs() is always enough).
+ *
+ *  Memory.  Every pointer inside the structs, and every workspace, is
+ *  device memory owned by the caller.  The structs themselves are read on
+ *  the host during the call and may be freed once it returns.  No entry
+ *  point allocates device memory, except morph_batch_plan_create (which owns
+ *  what it allocates until morph_batch_plan_destroy) and the debugging check
+ *  morph_rle_validate.  dst must not overlap
+ *  src (MORPH_E_ALIAS).
+ *
+ *  Streams and errors.  Work is queued on `stream` and runs asynchronously;
+ *  a return of MORPH_OK means the work was queued.  Argument errors are
+ *  detected on the host before anything is queued and return a negative
+ *  code; launch failures return MORPH_E_HIP (morph_last_hip_error() gives the
+ *  HIP message of the calling thread's last failure).
+ * ----------------------------------------------------------------------------
+ */
+#ifndef MORPH_H
+#define MORPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *morph_stream_t;   /* a hipStream_t; NULL = default stream */
+
+enum {
+    MORPH_OK = 0,
+    MORPH_E_INVAL = -1,          /* null pointer, non-positive size, bad element, bad stride */
+    MORPH_E_SHAPE = -2,          /* dst and src sizes differ */
+    MORPH_E_ALIAS = -3,          /* dst memory overlaps src memory */
+    MORPH_E_WORKSPACE = -4,      /* workspace smaller than morph_workspace_bytes() */
+    MORPH_E_NONCANONICAL = -5,   /* morph_rle_validate: runs not in the canonical form */
+    MORPH_E_CAPACITY = -6,       /* run capacity below what the call can guarantee */
+    MORPH_E_HIP = -7,            /* a HIP call failed */
+    MORPH_E_UNSUPPORTED = -8     /* outside what the library implements */
+};
+
+enum { MORPH_ERODE = 0, MORPH_DILATE = 1, MORPH_OPEN = 2, MORPH_CLOSE = 3 };
+enum { MORPH_PACKED = 0, MORPH_RLE = 1 };
+
+typedef struct {
+    uint64_t *words;
+    int32_t width, height, stride_words;
+    int32_t npages;                      /* >= 1 */
+} morph_bitmap_t;
+
+typedef struct {
+    int32_t width, height;
+    int32_t npages;                      /* >= 1 */
+    int32_t *row_ptr;                    /* npages*height + 1 entries */
+    int32_t *runs;                       /* 2*capacity entries */
+    int64_t capacity;
+} morph_rle_t;
+
+typedef struct { int32_t w, h, cx, cy; } morph_se_t;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Version string and a description of the device the library runs on. */
+const char *morph_version(void);
+/* Message for an error code. */
+const char *morph_strerror(int code);
+/* Message of the calling thread's last HIP failure ("" if none). */
+const char *morph_last_hip_error(void);
+
+/* ---- packed bitmaps ----------------------------------------------------- */
+/*
+ * Rectangle erosion / dilation / opening / closing of packed bitmaps
+ * (sections "Efficient Binary Decompositions" and "2D Morphological
+ * Operators for Rectangular Masks": separable row and column passes, each a
+ * logarithmic decomposition into shifted word-wise AND (erosion) or OR
+ * (dilation)).  dst and src must have equal width, height and npages;
+ * strides may differ.  ws/ws_bytes: device workspace of at least
+ * morph_workspace_bytes(op, MORPH_PACKED, ...) bytes (0 for most elements;
+ * ws may then be NULL).
+ */
+int morph_erode_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                            void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_dilate_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                             void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_open_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                           void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_close_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                            void *ws, size_t ws_bytes, morph_stream_t stream);
+
+/* ---- run-length images -------------------------------------------------- */
+/*
+ * The same four operations on run-length images (section "2D Morphological
+ * Operators for Rectangular Masks", third strategy: within-line operations
+ * first -- runs shrink, grow and merge, section "Within-Line Morphological
+ * Operations" -- then between-line operations, the intersection (erosion)
+ * or union (dilation) of the run lists of h consecutive rows, computed by
+ * logarithmic decomposition into pairwise merges, sections "Between Line
+ * Boolean Operations" and "Efficient Binary Decompositions").
+ * dst->capacity must be at least morph_rle_max_runs(width, height*npages)
+ * (MORPH_E_CAPACITY otherwise).  ws: at least morph_rle_workspace_bytes(op,
+ * width, height, npages, se) bytes.  Images whose worst case,
+ * npages*(height+h-1)*ceil(width/2) runs, reaches 2^31 give
+ * MORPH_E_UNSUPPORTED.
+ */
+int morph_erode_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
+                         void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_dilate_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
+                          void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_open_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
+                        void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_close_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
+                         void *ws, size_t ws_bytes, morph_stream_t stream);
+
+/* ---- conversion (section "Conversion Between Image Formats") ------------ */
+/*
+ * Packed bitmap -> run-length image: the maximal runs of every row.  The run
+ * count is written to dst->row_ptr[npages*height] even when it exceeds
+ * dst->capacity (then runs past capacity are dropped).  ws: at least
+ * morph_pack_to_rle_workspace_bytes(width, height*npages) bytes.
+ */
+int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src,
+                      void *ws, size_t ws_bytes, morph_stream_t stream);
+/* Run-length image -> packed bitmap (pad bits 0).  src must be canonical. */
+int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_stream_t stream);
+
+/* ---- sizes and checks --------------------------------------------------- */
+/* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
+ * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
+ * height*npages; for a run-length stack use morph_rle_workspace_bytes. */
+size_t morph_workspace_bytes(int op, int repr, int32_t width, int32_t height, morph_se_t se);
+/* Workspace bytes of a run-length operation on npages stacked pages. */
+size_t morph_rle_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se);
+/* Workspace bytes morph_pack_to_rle needs (height counts all stacked pages). */
+size_t morph_pack_to_rle_workspace_bytes(int32_t width, int32_t height);
+/* Most runs an image of this size can have: height * ceil(width/2). */
+int64_t morph_rle_max_runs(int32_t width, int32_t height);
+/* Synchronous check (waits for `stream`) that r is canonical, for debugging:
+ * MORPH_OK or MORPH_E_NONCANONICAL.  It allocates (and frees) a 4-byte
+ * device flag, the one exception to the no-allocation rule besides batch
+ * plans. */
+int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream);
+
+/* ---- batches of uneven pages (one persistent launch) -------------------- */
+/*
+ * A batch plan runs many packed pages of different sizes, each with its own
+ * operation and element, as one persistent kernel launch (captured in a
+ * HIP graph on first run and replayed afterwards).  Tiles of every page go
+ * into one work queue; the tile shape per page comes from `tile_rows` /
+ * `strip_words` of its descriptor (0 = library default).
+ */
+typedef struct {
+    morph_bitmap_t dst, src;             /* npages must be 1 */
+    int32_t op;                          /* MORPH_ERODE .. MORPH_CLOSE */
+    morph_se_t se;
+    int32_t tile_rows, strip_words;      /* 0 = default */
+} morph_page_desc_t;
+
+typedef struct morph_batch_plan morph_batch_plan_t;
+
+/* Builds the tile queue for n pages (descs in host memory) and uploads it.
+ * Fails with MORPH_E_UNSUPPORTED for an element the single-launch kernel
+ * cannot take (w > 129 or a side of the origin more than 64 pixels wide,
+ * or too tall for a tile); run such pages with the per-page calls. */
+int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *descs, int32_t n,
+                            morph_stream_t stream);
+/* Runs the whole batch: one launch (graph replay when use_graph != 0). */
+int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t stream);
+/* Number of tiles in the plan. */
+int64_t morph_batch_tiles(const morph_batch_plan_t *plan);
+void morph_batch_plan_destroy(morph_batch_plan_t *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MORPH_H */

@@ -1,0 +1,393 @@
+"""Binary and run-length morphology on MI355X (gfx950): Python binding.
+
+Every function named ``morph_*`` here marshals its arguments and calls the
+entry point of the same name in ``libmorph.so`` (declared, with its full
+contract, in ``include/morph.h``).  PyTorch only supplies device memory and
+streams; all work runs in the library's HIP kernels.  There is no other
+implementation behind this module: if the library is missing, importing the
+package fails.
+
+Images:
+
+* :class:`Bitmap` -- packed rows of 64-bit words (pixel x of a row is bit
+  x & 63 of word x >> 6), held in an int64 torch tensor of shape
+  ``(npages * height, stride_words)``.
+* :class:`RLE` -- run-length rows in CSR form: ``row_ptr`` (int32,
+  ``npages * height + 1``) and ``runs`` (int32, ``(capacity, 2)``) of
+  half-open ``[start, end)`` intervals.
+
+Structuring elements are ``(w, h, cx, cy)``: a w-wide, h-tall rectangle
+whose origin is column cx, row cy of it (see :func:`se`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "Bitmap", "RLE", "MorphError", "se", "OPS",
+    "morph_version", "morph_strerror", "morph_last_hip_error",
+    "morph_erode_rect_packed", "morph_dilate_rect_packed", "morph_open_rect_packed",
+    "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
+    "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
+    "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
+    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan",
+    "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmorph.so")
+
+OPS = ("erode", "dilate", "open", "close")
+MORPH_ERODE, MORPH_DILATE, MORPH_OPEN, MORPH_CLOSE = range(4)
+MORPH_PACKED, MORPH_RLE = 0, 1
+
+ERRORS = {
+    0: "MORPH_OK", -1: "MORPH_E_INVAL", -2: "MORPH_E_SHAPE", -3: "MORPH_E_ALIAS",
+    -4: "MORPH_E_WORKSPACE", -5: "MORPH_E_NONCANONICAL", -6: "MORPH_E_CAPACITY",
+    -7: "MORPH_E_HIP", -8: "MORPH_E_UNSUPPORTED",
+}
+
+
+class morph_bitmap_t(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("stride_words", ctypes.c_int32), ("npages", ctypes.c_int32)]
+
+
+class morph_rle_t(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("npages", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("runs", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class morph_se_t(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32)]
+
+
+class morph_page_desc_t(ctypes.Structure):
+    _fields_ = [("dst", morph_bitmap_t), ("src", morph_bitmap_t), ("op", ctypes.c_int32),
+                ("se", morph_se_t), ("tile_rows", ctypes.c_int32), ("strip_words", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("%s is not built (run __graft_entry__.build() or "
+                          "python paper_0712_0121_amd/_build.py)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    BM, RL, SE = ctypes.POINTER(morph_bitmap_t), ctypes.POINTER(morph_rle_t), morph_se_t
+    sig = {
+        "morph_version": (ctypes.c_char_p, []),
+        "morph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "morph_last_hip_error": (ctypes.c_char_p, []),
+        "morph_pack_to_rle": (ctypes.c_int, [RL, BM, P, SZ, P]),
+        "morph_rle_to_pack": (ctypes.c_int, [BM, RL, P]),
+        "morph_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, SE]),
+        "morph_rle_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
+        "morph_pack_to_rle_workspace_bytes": (SZ, [I32, I32]),
+        "morph_rle_max_runs": (I64, [I32, I32]),
+        "morph_rle_validate": (ctypes.c_int, [RL, P]),
+        "morph_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(morph_page_desc_t), I32, P]),
+        "morph_batch_run": (ctypes.c_int, [P, I32, P]),
+        "morph_batch_tiles": (I64, [P]),
+        "morph_batch_plan_destroy": (None, [P]),
+    }
+    for op in OPS:
+        sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
+        sig["morph_%s_rect_rle" % op] = (ctypes.c_int, [RL, RL, SE, P, SZ, P])
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)          # AttributeError here = symbol missing
+        f.restype = res
+        f.argtypes = args
+    return lib, sorted(sig)
+
+
+_lib, SYMBOLS = _load()
+
+
+class MorphError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = "%s: %s (%s)" % (where, _lib.morph_strerror(code).decode(), ERRORS.get(code, code))
+        if code == -7:
+            msg += ": " + _lib.morph_last_hip_error().decode()
+        super().__init__(msg)
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise MorphError(code, where)
+
+
+def se(w: int, h: int, cx: int | None = None, cy: int | None = None):
+    """A w x h rectangle; the origin defaults to (w // 2, h // 2)."""
+    return (int(w), int(h), int(w) // 2 if cx is None else int(cx), int(h) // 2 if cy is None else int(cy))
+
+
+def _se(s) -> morph_se_t:
+    if isinstance(s, morph_se_t):
+        return s
+    w, h, cx, cy = s
+    return morph_se_t(int(w), int(h), int(cx), int(cy))
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ws(ws):
+    if ws is None:
+        return None, 0
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+class Bitmap:
+    """Packed image(s) in device memory: words is an int64 tensor of shape
+    (npages*height, stride_words); npages equal-size pages are stacked."""
+
+    def __init__(self, words: torch.Tensor, width: int, height: int, npages: int = 1):
+        if words.dtype != torch.int64 or words.dim() != 2 or not words.is_contiguous():
+            raise ValueError("words must be a contiguous 2-D int64 tensor")
+        if words.shape[0] != height * npages:
+            raise ValueError("words must have npages*height rows")
+        self.words, self.width, self.height, self.npages = words, int(width), int(height), int(npages)
+
+    @property
+    def stride(self) -> int:
+        return self.words.shape[1]
+
+    @classmethod
+    def empty(cls, width, height, npages=1, stride=None, device="cuda"):
+        stride = (width + 63) // 64 if stride is None else stride
+        return cls(torch.empty((height * npages, stride), dtype=torch.int64, device=device),
+                   width, height, npages)
+
+    @classmethod
+    def from_words(cls, words_np, width, npages=1, device="cuda"):
+        """From a host (rows, stride) uint64 array."""
+        import numpy as np
+        w = torch.from_numpy(np.ascontiguousarray(words_np).view(np.int64)).to(device)
+        return cls(w, width, w.shape[0] // npages, npages)
+
+    def to_numpy(self):
+        """Host copy as (rows, stride) uint64."""
+        import numpy as np
+        return self.words.cpu().numpy().view(np.uint64)
+
+    def struct(self) -> morph_bitmap_t:
+        return morph_bitmap_t(self.words.data_ptr(), self.width, self.height, self.stride, self.npages)
+
+
+class RLE:
+    """Run-length image(s) in device memory (CSR over rows)."""
+
+    def __init__(self, row_ptr: torch.Tensor, runs: torch.Tensor, width: int, height: int, npages: int = 1):
+        if row_ptr.dtype != torch.int32 or runs.dtype != torch.int32:
+            raise ValueError("row_ptr and runs must be int32")
+        if row_ptr.numel() != height * npages + 1:
+            raise ValueError("row_ptr must have npages*height+1 entries")
+        if runs.dim() != 2 or runs.shape[1] != 2 or not runs.is_contiguous():
+            raise ValueError("runs must be a contiguous (capacity, 2) tensor")
+        self.row_ptr, self.runs = row_ptr, runs
+        self.width, self.height, self.npages = int(width), int(height), int(npages)
+
+    @property
+    def capacity(self) -> int:
+        return self.runs.shape[0]
+
+    @classmethod
+    def empty(cls, width, height, npages=1, capacity=None, device="cuda"):
+        if capacity is None:
+            capacity = morph_rle_max_runs(width, height * npages)
+        return cls(torch.empty(height * npages + 1, dtype=torch.int32, device=device),
+                   torch.empty((max(int(capacity), 1), 2), dtype=torch.int32, device=device),
+                   width, height, npages)
+
+    @classmethod
+    def from_host(cls, row_ptr, runs, width, height, npages=1, capacity=None, device="cuda"):
+        import numpy as np
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int32)).to(device)
+        rr = np.ascontiguousarray(runs, dtype=np.int32).reshape(-1, 2)
+        cap = max(rr.shape[0], 1) if capacity is None else int(capacity)
+        t = torch.zeros((cap, 2), dtype=torch.int32, device=device)
+        if rr.shape[0]:
+            t[: rr.shape[0]] = torch.from_numpy(rr).to(device)
+        return cls(rp, t, width, height, npages)
+
+    def nruns(self) -> int:
+        return int(self.row_ptr[-1].item())
+
+    def to_host(self):
+        """(row_ptr, runs[:n]) as numpy int32 arrays."""
+        rp = self.row_ptr.cpu().numpy()
+        n = int(rp[-1])
+        return rp, self.runs[:n].cpu().numpy()
+
+    def struct(self) -> morph_rle_t:
+        return morph_rle_t(self.width, self.height, self.npages, self.row_ptr.data_ptr(),
+                           self.runs.data_ptr(), self.capacity)
+
+
+# ---------------------------------------------------------------- entry points
+def morph_version() -> str:
+    return _lib.morph_version().decode()
+
+
+def morph_strerror(code: int) -> str:
+    return _lib.morph_strerror(code).decode()
+
+
+def morph_last_hip_error() -> str:
+    return _lib.morph_last_hip_error().decode()
+
+
+def _packed_entry(op):
+    name = "morph_%s_rect_packed" % op
+    f = getattr(_lib, name)
+
+    def call(dst: Bitmap, src: Bitmap, s, ws=None, stream=None):
+        d, r = dst.struct(), src.struct()
+        p, n = _ws(ws)
+        _check(f(ctypes.byref(d), ctypes.byref(r), _se(s), p, n, _stream(stream)), name)
+    call.__name__ = name
+    call.__doc__ = "Calls %s (include/morph.h)." % name
+    return call
+
+
+def _rle_entry(op):
+    name = "morph_%s_rect_rle" % op
+    f = getattr(_lib, name)
+
+    def call(dst: RLE, src: RLE, s, ws=None, stream=None):
+        d, r = dst.struct(), src.struct()
+        p, n = _ws(ws)
+        _check(f(ctypes.byref(d), ctypes.byref(r), _se(s), p, n, _stream(stream)), name)
+    call.__name__ = name
+    call.__doc__ = "Calls %s (include/morph.h)." % name
+    return call
+
+
+morph_erode_rect_packed = _packed_entry("erode")
+morph_dilate_rect_packed = _packed_entry("dilate")
+morph_open_rect_packed = _packed_entry("open")
+morph_close_rect_packed = _packed_entry("close")
+morph_erode_rect_rle = _rle_entry("erode")
+morph_dilate_rect_rle = _rle_entry("dilate")
+morph_open_rect_rle = _rle_entry("open")
+morph_close_rect_rle = _rle_entry("close")
+PACKED = {op: globals()["morph_%s_rect_packed" % op] for op in OPS}
+RLE_OPS = {op: globals()["morph_%s_rect_rle" % op] for op in OPS}
+
+
+def morph_pack_to_rle(dst: RLE, src: Bitmap, ws=None, stream=None):
+    d, r = dst.struct(), src.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(r), p, n, _stream(stream)),
+           "morph_pack_to_rle")
+
+
+def morph_rle_to_pack(dst: Bitmap, src: RLE, stream=None):
+    d, r = dst.struct(), src.struct()
+    _check(_lib.morph_rle_to_pack(ctypes.byref(d), ctypes.byref(r), _stream(stream)), "morph_rle_to_pack")
+
+
+def morph_workspace_bytes(op, repr_, width, height, s) -> int:
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    return int(_lib.morph_workspace_bytes(op, int(repr_), int(width), int(height), _se(s)))
+
+
+def morph_rle_workspace_bytes(op, width, height, npages, s) -> int:
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    return int(_lib.morph_rle_workspace_bytes(op, int(width), int(height), int(npages), _se(s)))
+
+
+def morph_pack_to_rle_workspace_bytes(width, height) -> int:
+    return int(_lib.morph_pack_to_rle_workspace_bytes(int(width), int(height)))
+
+
+def morph_rle_max_runs(width, height) -> int:
+    return int(_lib.morph_rle_max_runs(int(width), int(height)))
+
+
+def morph_rle_validate(r: RLE, stream=None) -> int:
+    s = r.struct()
+    return int(_lib.morph_rle_validate(ctypes.byref(s), _stream(stream)))
+
+
+class BatchPlan:
+    """Many packed pages, each with its own operation and element, run as one
+    persistent launch (morph_batch_plan_create / morph_batch_run)."""
+
+    def __init__(self, items, stream=None):
+        """items: iterable of (dst Bitmap, src Bitmap, op, se[, tile_rows, strip_words])."""
+        items = list(items)
+        arr = (morph_page_desc_t * max(1, len(items)))()
+        self._keep = []
+        for i, it in enumerate(items):
+            dst, src, op, s = it[:4]
+            tr, sw = (it[4], it[5]) if len(it) >= 6 else (0, 0)
+            arr[i] = morph_page_desc_t(dst.struct(), src.struct(), OPS.index(op) if isinstance(op, str) else op,
+                                       _se(s), int(tr), int(sw))
+            self._keep.append((dst, src))
+        h = ctypes.c_void_p()
+        _check(_lib.morph_batch_plan_create(ctypes.byref(h), arr, len(items), _stream(stream)),
+               "morph_batch_plan_create")
+        self._h = h
+
+    @property
+    def tiles(self) -> int:
+        return int(_lib.morph_batch_tiles(self._h))
+
+    def run(self, use_graph: bool = True, stream=None):
+        _check(_lib.morph_batch_run(self._h, 1 if use_graph else 0, _stream(stream)), "morph_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.morph_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- conveniences
+def _alloc_ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device) if nbytes else None
+
+
+def rect_packed(op: str, src: Bitmap, s, dst: Bitmap | None = None, stream=None) -> Bitmap:
+    """op in OPS on a packed image; allocates dst and workspace with torch."""
+    if dst is None:
+        dst = Bitmap.empty(src.width, src.height, src.npages, device=src.words.device)
+    ws = _alloc_ws(morph_workspace_bytes(op, MORPH_PACKED, src.width, src.height * src.npages, s),
+                   src.words.device)
+    PACKED[op](dst, src, s, ws, stream)
+    return dst
+
+
+def rect_rle(op: str, src: RLE, s, dst: RLE | None = None, stream=None) -> RLE:
+    if dst is None:
+        dst = RLE.empty(src.width, src.height, src.npages, device=src.row_ptr.device)
+    ws = _alloc_ws(morph_rle_workspace_bytes(op, src.width, src.height, src.npages, s), src.row_ptr.device)
+    RLE_OPS[op](dst, src, s, ws, stream)
+    return dst
+
+
+def pack_to_rle(src: Bitmap, capacity=None, stream=None) -> RLE:
+    dst = RLE.empty(src.width, src.height, src.npages, capacity=capacity, device=src.words.device)
+    ws = _alloc_ws(morph_pack_to_rle_workspace_bytes(src.width, src.height * src.npages), src.words.device)
+    morph_pack_to_rle(dst, src, ws, stream)
+    return dst
+
+
+def rle_to_pack(src: RLE, stride=None, stream=None) -> Bitmap:
+    dst = Bitmap.empty(src.width, src.height, src.npages, stride=stride, device=src.row_ptr.device)
+    morph_rle_to_pack(dst, src, stream)
+    return dst

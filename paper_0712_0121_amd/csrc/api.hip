@@ -1,0 +1,508 @@
+// C interface: argument checks, decomposition of an operation into kernel
+// launches, workspace sizing, batch plans.  Declarations and the contract
+// of every entry point are in include/morph.h.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace morph {
+
+static thread_local char g_hip_err[256] = "";
+
+void set_hip_error(hipError_t e)
+{
+    std::snprintf(g_hip_err, sizeof g_hip_err, "%s (%d)", hipGetErrorString(e), (int)e);
+}
+
+// ------------------------------------------------------------ pass planning
+// A rectangle operation is a sequence of erosion passes, each in the image
+// domain (dom 0) or in the complement domain (dom 1: dilation by B is the
+// complement of erosion of the complement by the reflected element B^).
+// An element whose origin is more than 64 pixels from a side of the row
+// window, or taller than the vertical limit, is split by the composition
+// law  op_{B1 (+) B2} = op_{B2} . op_{B1}  with
+// B1 (+) B2 = (w1+w2-1, h1+h2-1, cx1+cx2, cy1+cy2).
+struct Pass {
+    Stage st;
+    int dom;
+};
+
+constexpr int kVReachMax = 128;
+
+static void decompose(Stage B, int dom, std::vector<Pass> &out)
+{
+    int l = B.cx, r = B.w - 1 - B.cx, t = B.cy, b = B.h - 1 - B.cy;
+    bool first = true;
+    while (first || l > 0 || r > 0 || t > 0 || b > 0) {
+        const int pl = std::min(l, kReachMax), pr = std::min(r, kReachMax);
+        const int pt = std::min(t, kVReachMax), pb = std::min(b, kVReachMax);
+        out.push_back({Stage{pl + pr + 1, pt + pb + 1, pl, pt}, dom});
+        l -= pl; r -= pr; t -= pt; b -= pb;
+        first = false;
+    }
+}
+
+static std::vector<Pass> op_passes(int op, morph_se_t se)
+{
+    const Stage B{se.w, se.h, se.cx, se.cy};
+    const Stage R{se.w, se.h, se.w - 1 - se.cx, se.h - 1 - se.cy};
+    std::vector<Pass> v;
+    switch (op) {
+    case MORPH_ERODE: decompose(B, 0, v); break;
+    case MORPH_DILATE: decompose(R, 1, v); break;
+    case MORPH_OPEN: decompose(B, 0, v); decompose(R, 1, v); break;
+    case MORPH_CLOSE: decompose(R, 1, v); decompose(B, 0, v); break;
+    }
+    return v;
+}
+
+struct Launch {
+    RectPage p;
+};
+
+// Groups passes into launches (two per launch when a tile fits both) and
+// fills in complement flags and tile shapes.  Buffers are set by the caller.
+static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int tile_rows,
+                          int strip_words, std::vector<Launch> &out)
+{
+    const std::vector<Pass> ps = op_passes(op, se);
+    const int nw = (W + 63) / 64;
+    RectPage base{};
+    base.W = W;
+    base.H = H;
+    base.nw = nw;
+    base.padmask = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
+    int stored_dom = 0;
+    size_t i = 0;
+    while (i < ps.size()) {
+        RectPage p = base;
+        bool fused = false;
+        if (i + 1 < ps.size()) {
+            p.nst = 2;
+            p.st[0] = ps[i].st;
+            p.st[1] = ps[i + 1].st;
+            RectPage q = p;
+            if (plan_tiles(q, tile_rows, strip_words, npages) && q.TR >= 8) {
+                p = q;
+                fused = true;
+            }
+        }
+        if (!fused) {
+            p.nst = 1;
+            p.st[0] = ps[i].st;
+            if (!plan_tiles(p, tile_rows, strip_words, npages)) return false;
+        }
+        const size_t last = i + p.nst - 1;
+        const int out_dom = (last + 1 < ps.size()) ? ps[last + 1].dom : 0;
+        p.in_c = ps[i].dom != stored_dom;
+        p.mid_c = (p.nst == 2) && (ps[i + 1].dom != ps[i].dom);
+        p.out_c = ps[last].dom != out_dom;
+        stored_dom = out_dom;
+        out.push_back(Launch{p});
+        i = last + 1;
+    }
+    return true;
+}
+
+static size_t image_bytes(int W, int rows) { return (size_t)((W + 63) / 64) * (size_t)rows * 8; }
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static bool se_ok(morph_se_t se)
+{
+    return se.w >= 1 && se.h >= 1 && se.cx >= 0 && se.cy >= 0 && se.cx < se.w && se.cy < se.h;
+}
+
+static bool bitmap_ok(const morph_bitmap_t *b)
+{
+    if (!b || !b->words) return false;
+    if (b->width < 1 || b->height < 1 || b->npages < 1) return false;
+    if (b->stride_words < (b->width + 63) / 64) return false;
+    if (((uintptr_t)b->words) & 7) return false;
+    if ((long long)b->height * b->npages > 0x7fffffffLL) return false;
+    return true;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+static size_t bitmap_extent(const morph_bitmap_t *b)
+{
+    const size_t rows = (size_t)b->height * b->npages;
+    return ((rows - 1) * b->stride_words + (b->width + 63) / 64) * 8;
+}
+
+static int rect_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                       void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!bitmap_ok(dst) || !bitmap_ok(src) || !se_ok(se)) return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
+    std::vector<Launch> L;
+    if (!plan_launches(op, se, src->width, src->height, src->npages, 0, 0, L))
+        return MORPH_E_UNSUPPORTED;
+    const int W = src->width, H = src->height, P = src->npages, nw = (W + 63) / 64;
+    const size_t img = round256(image_bytes(W, H * P));
+    const size_t need = L.size() <= 1 ? 0 : (L.size() == 2 ? img : 2 * img);
+    if (need > 0 && (ws == nullptr || ws_bytes < need)) return MORPH_E_WORKSPACE;
+    uint64_t *tmp[2] = {(uint64_t *)ws, (uint64_t *)((char *)ws + img)};
+    const uint64_t *in = src->words;
+    int in_stride = src->stride_words;
+    for (size_t k = 0; k < L.size(); k++) {
+        RectPage p = L[k].p;
+        const bool lastl = k + 1 == L.size();
+        uint64_t *out = lastl ? dst->words : tmp[k & 1];
+        const int out_stride = lastl ? dst->stride_words : nw;
+        p.src = in;
+        p.dst = out;
+        p.sstride = in_stride;
+        p.dstride = out_stride;
+        p.src_page_words = (long long)in_stride * H;
+        p.dst_page_words = (long long)out_stride * H;
+        hipError_t e = launch_rect(p, P, stream);
+        if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+        in = out;
+        in_stride = out_stride;
+    }
+    return MORPH_OK;
+}
+
+// ------------------------------------------------------------------ batches
+}  // namespace morph
+
+struct morph_batch_plan {
+    morph::RectPage *pages_dev = nullptr;
+    morph::TileRef *tiles_dev = nullptr;
+    int *queue_dev = nullptr;
+    int ntiles = 0;
+    int nblocks = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+using namespace morph;
+
+extern "C" {
+
+const char *morph_version(void) { return "morph 0.1 (gfx950, HIP)"; }
+
+const char *morph_strerror(int code)
+{
+    switch (code) {
+    case MORPH_OK: return "ok";
+    case MORPH_E_INVAL: return "invalid argument";
+    case MORPH_E_SHAPE: return "dst and src sizes differ";
+    case MORPH_E_ALIAS: return "dst overlaps src";
+    case MORPH_E_WORKSPACE: return "workspace too small";
+    case MORPH_E_NONCANONICAL: return "run-length image not canonical";
+    case MORPH_E_CAPACITY: return "run capacity too small";
+    case MORPH_E_HIP: return "HIP call failed";
+    case MORPH_E_UNSUPPORTED: return "not supported";
+    default: return "unknown error";
+    }
+}
+
+const char *morph_last_hip_error(void) { return g_hip_err; }
+
+int morph_erode_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                            void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_packed(MORPH_ERODE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_dilate_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                             void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_packed(MORPH_DILATE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_open_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                           void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_packed(MORPH_OPEN, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_close_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
+                            void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_packed(MORPH_CLOSE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int64_t morph_rle_max_runs(int32_t width, int32_t height)
+{
+    if (width < 1 || height < 1) return 0;
+    return (int64_t)height * ((width + 1) / 2);
+}
+
+size_t morph_workspace_bytes(int op, int repr, int32_t width, int32_t height, morph_se_t se)
+{
+    if (width < 1 || height < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE) return 0;
+    if (repr == MORPH_PACKED) {
+        std::vector<Launch> L;
+        if (!plan_launches(op, se, width, height, 1, 0, 0, L)) return 0;
+        const size_t img = round256(image_bytes(width, height));
+        return L.size() <= 1 ? 0 : (L.size() == 2 ? img : 2 * img);
+    }
+    return rle_op_workspace(op, width, height, height, se);
+}
+
+// ---- batch plans
+int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *descs, int32_t n,
+                            morph_stream_t stream)
+{
+    (void)stream;
+    if (!plan || (!descs && n > 0) || n < 0) return MORPH_E_INVAL;
+    *plan = nullptr;
+    std::vector<RectPage> pages;
+    std::vector<double> cost;
+    for (int i = 0; i < n; i++) {
+        const morph_page_desc_t &d = descs[i];
+        if (!bitmap_ok(&d.dst) || !bitmap_ok(&d.src) || !se_ok(d.se) || d.op < MORPH_ERODE ||
+            d.op > MORPH_CLOSE || d.src.npages != 1 || d.dst.npages != 1)
+            return MORPH_E_INVAL;
+        if (d.dst.width != d.src.width || d.dst.height != d.src.height) return MORPH_E_SHAPE;
+        if (overlap(d.dst.words, bitmap_extent(&d.dst), d.src.words, bitmap_extent(&d.src)))
+            return MORPH_E_ALIAS;
+        std::vector<Launch> L;
+        if (!plan_launches(d.op, d.se, d.src.width, d.src.height, n, d.tile_rows, d.strip_words, L) ||
+            L.size() != 1)
+            return MORPH_E_UNSUPPORTED;
+        RectPage p = L[0].p;
+        if (!tile_fits(p)) return MORPH_E_UNSUPPORTED;
+        p.src = d.src.words;
+        p.dst = d.dst.words;
+        p.sstride = d.src.stride_words;
+        p.dstride = d.dst.stride_words;
+        p.src_page_words = 0;
+        p.dst_page_words = 0;
+        pages.push_back(p);
+        double hs = 0, lg = 0;
+        for (int s = 0; s < p.nst; s++) {
+            hs += p.st[s].h - 1;
+            lg += 2 + std::log2((double)p.st[s].w) + std::log2((double)p.st[s].h);
+        }
+        cost.push_back((double)p.nw * (p.H + hs * p.nbands) * lg);
+    }
+    // expensive pages first (their tiles leave the queue first), each page's
+    // tiles in band order so neighbours run close together in time
+    std::vector<int> order(n);
+    for (int i = 0; i < n; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<TileRef> tiles;
+    for (int i : order)
+        for (int b = 0; b < pages[i].nbands; b++)
+            for (int s = 0; s < pages[i].nstrips; s++) tiles.push_back(TileRef{i, b, s, 0});
+    if (tiles.size() > 0x7fffffff) return MORPH_E_UNSUPPORTED;
+
+    morph_batch_plan_t *pl = new (std::nothrow) morph_batch_plan_t();
+    if (!pl) return MORPH_E_HIP;
+    hipError_t e = hipSuccess;
+    const size_t pb = std::max<size_t>(1, pages.size()) * sizeof(RectPage);
+    const size_t tb = std::max<size_t>(1, tiles.size()) * sizeof(TileRef);
+    if ((e = hipMalloc(&pl->pages_dev, pb)) != hipSuccess ||
+        (e = hipMalloc(&pl->tiles_dev, tb)) != hipSuccess ||
+        (e = hipMalloc(&pl->queue_dev, 256)) != hipSuccess ||
+        (n > 0 && (e = hipMemcpy(pl->pages_dev, pages.data(), pages.size() * sizeof(RectPage),
+                                 hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!tiles.empty() && (e = hipMemcpy(pl->tiles_dev, tiles.data(), tiles.size() * sizeof(TileRef),
+                                          hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+        set_hip_error(e);
+        morph_batch_plan_destroy(pl);
+        return MORPH_E_HIP;
+    }
+    pl->ntiles = (int)tiles.size();
+    pl->nblocks = std::max(1, std::min(pl->ntiles, 2 * device_cu_count()));
+    *plan = pl;
+    return MORPH_OK;
+}
+
+int64_t morph_batch_tiles(const morph_batch_plan_t *plan) { return plan ? plan->ntiles : 0; }
+
+int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t stream)
+{
+    if (!plan) return MORPH_E_INVAL;
+    if (plan->ntiles == 0) return MORPH_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!use_graph) {
+        if ((e = launch_reset_counter(plan->queue_dev, s)) != hipSuccess ||
+            (e = launch_rect_batch(plan->pages_dev, plan->tiles_dev, plan->ntiles, plan->queue_dev,
+                                   plan->nblocks, s)) != hipSuccess) {
+            set_hip_error(e);
+            return MORPH_E_HIP;
+        }
+        return MORPH_OK;
+    }
+    if (!plan->exec) {
+        // the queue counter is cleared by a kernel inside the graph (no memset node)
+        hipStream_t cs = plan->capture_stream;
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            set_hip_error(e);
+            return MORPH_E_HIP;
+        }
+        hipError_t e1 = launch_reset_counter(plan->queue_dev, cs);
+        hipError_t e2 = launch_rect_batch(plan->pages_dev, plan->tiles_dev, plan->ntiles,
+                                          plan->queue_dev, plan->nblocks, cs);
+        e = hipStreamEndCapture(cs, &plan->graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+            set_hip_error(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e));
+            if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+            return MORPH_E_HIP;
+        }
+        if ((e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            set_hip_error(e);
+            plan->exec = nullptr;
+            return MORPH_E_HIP;
+        }
+    }
+    if ((e = hipGraphLaunch(plan->exec, s)) != hipSuccess) {
+        set_hip_error(e);
+        return MORPH_E_HIP;
+    }
+    return MORPH_OK;
+}
+
+void morph_batch_plan_destroy(morph_batch_plan_t *plan)
+{
+    if (!plan) return;
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    if (plan->capture_stream) hipStreamDestroy(plan->capture_stream);
+    if (plan->pages_dev) hipFree(plan->pages_dev);
+    if (plan->tiles_dev) hipFree(plan->tiles_dev);
+    if (plan->queue_dev) hipFree(plan->queue_dev);
+    delete plan;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ run-length API
+namespace morph {
+
+static bool rle_ok(const morph_rle_t *r)
+{
+    if (!r || !r->row_ptr) return false;
+    if (r->width < 1 || r->height < 1 || r->npages < 1 || r->capacity < 0) return false;
+    if (r->capacity > 0 && !r->runs) return false;
+    if ((long long)r->height * r->npages >= 0x7fffffffLL) return false;
+    return true;
+}
+
+static size_t rle_extent_rp(const morph_rle_t *r) { return ((size_t)r->height * r->npages + 1) * 4; }
+static size_t rle_extent_runs(const morph_rle_t *r) { return (size_t)r->capacity * 8; }
+
+static bool rle_alias(const morph_rle_t *a, const morph_rle_t *b)
+{
+    const size_t ar = rle_extent_rp(a), br = rle_extent_rp(b);
+    const size_t an = rle_extent_runs(a), bn = rle_extent_runs(b);
+    if (overlap(a->row_ptr, ar, b->row_ptr, br)) return true;
+    if (an && bn && overlap(a->runs, an, b->runs, bn)) return true;
+    if (bn && overlap(a->row_ptr, ar, b->runs, bn)) return true;
+    if (an && overlap(a->runs, an, b->row_ptr, br)) return true;
+    return false;
+}
+
+static int rect_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                    size_t ws_bytes, hipStream_t stream)
+{
+    if (!rle_ok(dst) || !rle_ok(src) || !se_ok(se)) return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    if (rle_alias(dst, src)) return MORPH_E_ALIAS;
+    const long long ext = (long long)src->npages * (src->height + (long long)se.h - 1);
+    if (ext * ((src->width + 1) / 2) >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
+    const size_t need = rle_op_workspace(op, src->width, src->height * src->npages, src->height, se);
+    if (!ws || ws_bytes < need) return MORPH_E_WORKSPACE;
+    hipError_t e = rle_rect_op(op, *dst, *src, se, ws, ws_bytes, stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+}  // namespace morph
+
+extern "C" {
+
+int morph_erode_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                         size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_rle(MORPH_ERODE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_dilate_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                          size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_rle(MORPH_DILATE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_open_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                        size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_rle(MORPH_OPEN, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+int morph_close_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                         size_t ws_bytes, morph_stream_t stream)
+{
+    return rect_rle(MORPH_CLOSE, dst, src, se, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t morph_rle_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se)
+{
+    if (width < 1 || height < 1 || npages < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return 0;
+    return rle_op_workspace(op, width, height * npages, height, se);
+}
+
+size_t morph_pack_to_rle_workspace_bytes(int32_t width, int32_t height)
+{
+    if (width < 1 || height < 1) return 0;
+    return ((size_t)height * 4 + 255) / 256 * 256 + scan_workspace(height);
+}
+
+int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src, void *ws, size_t ws_bytes,
+                      morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !bitmap_ok(src)) return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    const size_t ext = bitmap_extent(src);
+    if (overlap(dst->row_ptr, rle_extent_rp(dst), src->words, ext) ||
+        (dst->capacity && overlap(dst->runs, rle_extent_runs(dst), src->words, ext)))
+        return MORPH_E_ALIAS;
+    const size_t need = morph_pack_to_rle_workspace_bytes(src->width, src->height * src->npages);
+    if (!ws || ws_bytes < need) return MORPH_E_WORKSPACE;
+    hipError_t e = rle_from_packed(*dst, *src, ws, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_stream_t stream)
+{
+    if (!bitmap_ok(dst) || !rle_ok(src)) return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    const size_t ext = bitmap_extent(dst);
+    if (overlap(src->row_ptr, rle_extent_rp(src), dst->words, ext) ||
+        (src->capacity && overlap(src->runs, rle_extent_runs(src), dst->words, ext)))
+        return MORPH_E_ALIAS;
+    hipError_t e = rle_to_packed(*dst, *src, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
+{
+    if (!rle_ok(r)) return MORPH_E_INVAL;
+    hipError_t e = hipSuccess;
+    const int rc = rle_validate(*r, (hipStream_t)stream, &e);
+    if (rc == MORPH_E_HIP) set_hip_error(e);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/morph.h"
+
+namespace morph {
+
+// ------------------------------------------------------------------ packed
+// Geometry of the fused band kernel (one workgroup = one tile).
+constexpr int kThreads = 512;          // threads per workgroup
+constexpr int kLdsWords = 8192;        // 64 KiB of LDS per workgroup (two per CU)
+constexpr int kChunkMax = 16;          // rows a thread keeps in registers in the column pass
+constexpr int kWordsPerItem = 4;       // consecutive words one row-pass item produces
+constexpr int kItemsMax = 4;           // row-pass items a thread holds across a barrier
+constexpr int kReachMax = 64;          // pixels each side of the origin one pass can reach (row)
+constexpr int kStripMax = 64;          // default widest strip (words)
+
+// One erosion pass ("stage") of a rectangle operation.  Every operation is
+// run as erosions: dilation_B(A) = not erosion_B^(not A), with B^ the
+// reflected element, so outside pixels are always 1 inside the kernel.
+struct Stage {
+    int w, h, cx, cy;
+};
+
+// One page of a rectangle operation as the kernel sees it.
+struct RectPage {
+    const uint64_t *src;
+    uint64_t *dst;
+    int W, H, nw;             // pixels, rows, words per row = ceil(W/64)
+    int sstride, dstride;     // words
+    int nst;                  // 1 or 2 stages fused in the launch
+    Stage st[2];
+    int in_c, mid_c, out_c;   // complement the input / between stages / the output (0 or 1)
+    int TR, SW;               // tile rows, strip words
+    int nbands, nstrips;
+    uint64_t padmask;         // valid bits of the last word of a row
+    long long src_page_words, dst_page_words;  // stacked pages
+};
+
+// Tile planning (host).  Returns false if no tile shape fits.
+bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages);
+bool tile_fits(const RectPage &p);
+
+// Launch one fused pass over npages stacked pages.
+hipError_t launch_rect(const RectPage &p, int npages, hipStream_t stream);
+
+// Batched form: a device table of pages and a tile list.
+struct TileRef {
+    int page, band, strip, pad;
+};
+hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev, int ntiles,
+                             int *queue_dev, int nblocks, hipStream_t stream);
+hipError_t launch_reset_counter(int *queue_dev, hipStream_t stream);
+int device_cu_count();
+
+// ------------------------------------------------------------- run-length
+hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
+                           hipStream_t stream);
+hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipStream_t stream);
+size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t se);
+hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+size_t scan_workspace(int64_t n);
+int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
+
+void set_hip_error(hipError_t e);
+
+}  // namespace morph
