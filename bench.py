@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark: rectangle morphology of letter pages on one MI355X.
+
+One step runs the whole letter-page workload on a batch of pages that are
+already resident in HBM:
+
+* packed path: erode, dilate, open, close with the elements 1x31, 31x1, 3x3,
+  21x21 and 51x51 (h x w), each one launch over the whole stacked batch;
+* run-length path: bitmap -> runs, the same 20 operations on runs, runs ->
+  bitmap of the last result.
+
+It prints one JSON line: Gpixel/s over the step (pixels counted once per
+operation and path), the roofline of the dominant kernel measured with HIP
+events inside the timed region, and the CPU oracle timed on a sample of the
+same work.  Pages are synthetic (seeded), standing in for scanned 300 dpi
+letter pages.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+LETTER_W, LETTER_H = 2550, 3300
+LETTER_SES = [("1x31", (31, 1, 15, 0)), ("31x1", (1, 31, 0, 15)), ("3x3", (3, 3, 1, 1)),
+              ("21x21", (21, 21, 10, 10)), ("51x51", (51, 51, 25, 25))]
+OPS = ("erode", "dilate", "open", "close")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pages", type=int, default=256, help="letter pages per batch")
+    ap.add_argument("--distinct", type=int, default=16, help="distinct seeded pages in the batch")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU oracle sample time")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--latency-reps", type=int, default=30)
+    ap.add_argument("--only", choices=["all", "packed", "rle"], default="all",
+                    help="restrict the step (for profiling); the JSON value needs 'all'")
+    return ap.parse_args()
+
+
+def gen_batch(n, distinct):
+    import pagegen
+    pool = [pagegen.letter_page(2000 + i) for i in range(distinct)]
+    return pool, [pool[i % distinct] for i in range(n)]
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v), q))
+
+
+def cpu_baseline(pool, min_seconds):
+    """The oracle as it is: every operation of the workload on whole pages,
+    packed results by brute force, run-length results as encode(brute force
+    (decode(runs))), pages taken one by one until min_seconds have passed."""
+    import oracle
+    pages = 0
+    px = 0
+    t0 = time.perf_counter()
+    while True:
+        img = pool[pages % len(pool)].img
+        for _, se in LETTER_SES:
+            for op in OPS:
+                oracle.apply(op, img, se)
+        rp, runs = oracle.rle_encode(img)
+        for _, se in LETTER_SES:
+            for op in OPS:
+                oracle.rle_apply(op, rp, runs, img.shape[1], img.shape[0], se)
+        last = oracle.rle_encode(oracle.apply("close", img, LETTER_SES[-1][1]))
+        oracle.rle_decode(*last, img.shape[1], img.shape[0])
+        pages += 1
+        px += 2 * len(LETTER_SES) * len(OPS) * img.size
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d letter page(s) 2550x3300 through the full workload (20 ops brute force on "
+                      "bytes + 20 ops as encode(brute(decode(runs))) + conversions), %.1f s"
+                      % (pages, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (run --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0712_0121_amd as M
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B = args.pages
+    pool, batch = gen_batch(B, args.distinct)
+    W, H = LETTER_W, LETTER_H
+    nw = (W + 63) // 64
+    words_pool = [torch.from_numpy(p.words().view(np.int64)) for p in pool]
+    host = torch.cat([words_pool[i % len(pool)] for i in range(B)], dim=0)
+    src = M.Bitmap(host.to(dev), W, H, B)
+    dst = M.Bitmap.empty(W, H, B, device=dev)
+    back = M.Bitmap.empty(W, H, B, device=dev)
+    del host
+    max_runs = M.morph_rle_max_runs(W, H * B)
+    rle_src = M.RLE.empty(W, H, B, capacity=max_runs, device=dev)
+    rle_dst = M.RLE.empty(W, H, B, capacity=max_runs, device=dev)
+    ws_rle_n = max(M.morph_rle_workspace_bytes(op, W, H, B, se) for op in OPS for _, se in LETTER_SES)
+    ws_rle = torch.empty(ws_rle_n, dtype=torch.uint8, device=dev)
+    ws_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * B), dtype=torch.uint8, device=dev)
+    ws_pk_n = max(M.morph_workspace_bytes(op, 0, W, H * B, se) for op in OPS for _, se in LETTER_SES)
+    ws_pk = torch.empty(max(ws_pk_n, 1), dtype=torch.uint8, device=dev) if ws_pk_n else None
+    stream = torch.cuda.current_stream()
+
+    packed_jobs = [(op, name, se) for name, se in LETTER_SES for op in OPS]
+    do_packed = args.only in ("all", "packed")
+    do_rle = args.only in ("all", "rle")
+
+    def step(ev=None):
+        if do_packed:
+            for k, (op, _, se) in enumerate(packed_jobs):
+                if ev is not None:
+                    ev["pk"][k][0].record(stream)
+                M.PACKED[op](dst, src, se, ws_pk)
+                if ev is not None:
+                    ev["pk"][k][1].record(stream)
+        if do_rle:
+            if ev is not None:
+                ev["p2r"][0].record(stream)
+            M.morph_pack_to_rle(rle_src, src, ws_p2r)
+            if ev is not None:
+                ev["p2r"][1].record(stream)
+            for k, (op, _, se) in enumerate(packed_jobs):
+                if ev is not None:
+                    ev["rle"][k][0].record(stream)
+                M.RLE_OPS[op](rle_dst, rle_src, se, ws_rle)
+                if ev is not None:
+                    ev["rle"][k][1].record(stream)
+            if ev is not None:
+                ev["r2p"][0].record(stream)
+            M.morph_rle_to_pack(back, rle_dst)
+            if ev is not None:
+                ev["r2p"][1].record(stream)
+
+    def new_events():
+        E = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        return {"pk": [E() for _ in packed_jobs], "rle": [E() for _ in packed_jobs], "p2r": E(), "r2p": E()}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [new_events() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+
+    def avg(getter):
+        return float(np.mean([getter(e)[0].elapsed_time(getter(e)[1]) for e in evs]))
+
+    page_px = W * H
+    n_ops = len(packed_jobs)
+    px_step = (n_ops * B * page_px if do_packed else 0) + (n_ops * B * page_px if do_rle else 0)
+    out = {
+        "metric": "Gpixel/s rect erode/dilate/open/close (packed & RLE), letter pages",
+        "value": px_step / (dt / args.steps) / 1e9,
+        "unit": "Gpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+i32",
+        "data": "synthetic (seeded letter pages, %d distinct, resident in HBM)" % args.distinct,
+        "config": {"workload": "letter page 2550x3300 (40 words/row), batch of %d pages; erode, dilate, "
+                               "open, close x SE {1x31, 31x1, 3x3, 21x21, 51x51}; packed path and "
+                               "RLE path (bitmap->RLE, 20 ops on runs, RLE->bitmap)" % B,
+                   "pages": B, "width": W, "height": H, "only": args.only},
+    }
+    alg_bytes_pk = B * 2 * 8 * nw * H           # one read + one write of the batch
+    breakdown = {}
+    if do_packed:
+        pk_ms = [float(np.mean([e["pk"][k][0].elapsed_time(e["pk"][k][1]) for e in evs]))
+                 for k in range(n_ops)]
+        per = {"%s %s" % (op, name): round(m, 4) for (op, name, _), m in zip(packed_jobs, pk_ms)}
+        mean_ms = float(np.mean(pk_ms))
+        breakdown["packed"] = {"ms": sum(pk_ms), "gpixel_s": n_ops * B * page_px / (sum(pk_ms) / 1e3) / 1e9,
+                               "ms_per_op": per}
+        roof_pk = {"bound": "hbm", "kernel": "rect_kernel (fused band, one launch per op)",
+                   "achieved": alg_bytes_pk / (mean_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "traffic": None,
+                   "bytes_per_launch": alg_bytes_pk, "avg_launch_ms": mean_ms}
+        roof_pk["frac"] = roof_pk["achieved"] / HBM_PEAK_GBS
+        out["roofline"] = roof_pk
+    if do_rle:
+        rle_ms = [float(np.mean([e["rle"][k][0].elapsed_time(e["rle"][k][1]) for e in evs]))
+                  for k in range(n_ops)]
+        p2r = avg(lambda e: e["p2r"])
+        r2p = avg(lambda e: e["r2p"])
+        breakdown["rle"] = {"ms_ops": sum(rle_ms), "ms_pack_to_rle": p2r, "ms_rle_to_pack": r2p,
+                            "gpixel_s": n_ops * B * page_px / ((sum(rle_ms) + p2r + r2p) / 1e3) / 1e9,
+                            "ms_per_op": {"%s %s" % (op, name): round(m, 4)
+                                          for (op, name, _), m in zip(packed_jobs, rle_ms)},
+                            "runs_in": int(rle_src.row_ptr[-1].item())}
+    out["breakdown"] = breakdown
+
+    # single-page latency of the whole page workload (one page resident)
+    if args.only == "all" and args.latency_reps > 0:
+        one = M.Bitmap(src.words[:H], W, H, 1)
+        od = M.Bitmap.empty(W, H, 1, device=dev)
+        ob = M.Bitmap.empty(W, H, 1, device=dev)
+        r1 = M.RLE.empty(W, H, 1, device=dev)
+        r2 = M.RLE.empty(W, H, 1, device=dev)
+        w1 = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, 1, se) for op in OPS for _, se in LETTER_SES),
+                         dtype=torch.uint8, device=dev)
+        w2 = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
+        lat_pk, lat_all = [], []
+        for rep in range(args.latency_reps + 3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for op, _, se in packed_jobs:
+                M.PACKED[op](od, one, se)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            M.morph_pack_to_rle(r1, one, w2)
+            for op, _, se in packed_jobs:
+                M.RLE_OPS[op](r2, r1, se, w1)
+            M.morph_rle_to_pack(ob, r2)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep >= 3:
+                lat_pk.append((t1 - t) * 1e6)
+                lat_all.append((t2 - t) * 1e6)
+        out["page_latency_us"] = {"packed_20_ops": {"p50": percentile(lat_pk, 50), "p99": percentile(lat_pk, 99)},
+                                  "packed_and_rle_40_ops": {"p50": percentile(lat_all, 50),
+                                                            "p99": percentile(lat_all, 99)},
+                                  "reps": args.latency_reps}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pool, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

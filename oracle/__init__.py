@@ -56,8 +56,14 @@ def _load():
         lib.oracle_rle_count.restype = ctypes.c_int64
         lib.oracle_rle_encode.argtypes = [P, P, P, I, I]
         lib.oracle_rle_decode.argtypes = [P, P, P, I, I]
+        lib.oracle_threads.restype = I
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().oracle_threads())
 
 
 def _ptr(a: np.ndarray):

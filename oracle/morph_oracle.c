@@ -30,6 +30,19 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of threads the OpenMP loops below use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define PIX(img, W, x, y) ((img)[(size_t)(y) * (size_t)(W) + (size_t)(x)])
 

@@ -1,0 +1,160 @@
+"""The C-ABI library on the CPU (no GPU calls): it loads, exports every
+function include/morph.h declares, and rejects bad arguments on the host
+before anything is queued (the pointers below are host addresses and are
+never dereferenced because every call here fails validation)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_0712_0121_amd as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "morph.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(morph_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(M.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(M.SYMBOLS)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(M.morph_bitmap_t) == 24
+    assert ctypes.sizeof(M.morph_rle_t) == 40
+    assert M.morph_rle_t.row_ptr.offset == 16
+    assert ctypes.sizeof(M.morph_se_t) == 16
+
+
+def test_version_and_strerror():
+    assert "gfx950" in M.morph_version()
+    for code in range(-8, 1):
+        assert M.morph_strerror(code)
+    assert M.morph_strerror(-99) == "unknown error"
+
+
+def test_sizes():
+    assert M.morph_rle_max_runs(2550, 3300) == 3300 * 1275
+    assert M.morph_rle_max_runs(1, 1) == 1
+    assert M.morph_rle_max_runs(0, 5) == 0
+    assert M.morph_workspace_bytes("erode", 0, 2550, 3300, (51, 51, 25, 25)) == 0
+    # an element beyond one launch's reach needs intermediate images
+    assert M.morph_workspace_bytes("erode", 0, 2550, 3300, (300, 3, 150, 1)) >= 40 * 3300 * 8
+    assert M.morph_workspace_bytes("open", 0, 2550, 3300, (300, 3, 150, 1)) >= 2 * 40 * 3300 * 8
+    assert M.morph_pack_to_rle_workspace_bytes(2550, 3300) >= 3300 * 4
+    a = M.morph_rle_workspace_bytes("erode", 2550, 3300, 1, (41, 1, 20, 0))
+    b = M.morph_rle_workspace_bytes("open", 2550, 3300, 2, (41, 1, 20, 0))
+    assert b > a > 0
+    assert M.morph_rle_workspace_bytes("erode", 0, 3300, 1, (3, 3, 1, 1)) == 0
+
+
+class HostBuf:
+    """Host memory standing in for device pointers in calls that must fail."""
+
+    def __init__(self, nbytes):
+        self.a = np.zeros(max(nbytes, 8), np.uint8)
+
+    @property
+    def ptr(self):
+        return self.a.ctypes.data
+
+
+def bitmap(buf, W, H, stride=None, npages=1, off=0):
+    stride = (W + 63) // 64 if stride is None else stride
+    return M.morph_bitmap_t(buf.ptr + off, W, H, stride, npages)
+
+
+def call_packed(op, d, s, se, ws=None, n=0):
+    f = getattr(M._lib, "morph_%s_rect_packed" % op)
+    return f(ctypes.byref(d), ctypes.byref(s), M.morph_se_t(*se), ws, n, None)
+
+
+@pytest.mark.parametrize("op", M.OPS)
+def test_packed_argument_errors(op):
+    a, b = HostBuf(1 << 16), HostBuf(1 << 16)
+    ok_se = (3, 3, 1, 1)
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(b, 100, 10), (0, 3, 0, 1)) == -1
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(b, 100, 10), (3, 3, 3, 1)) == -1
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(b, 100, 10), (3, 3, 1, -1)) == -1
+    assert call_packed(op, bitmap(a, 100, 10, stride=1), bitmap(b, 100, 10), ok_se) == -1
+    assert call_packed(op, bitmap(a, 0, 10), bitmap(b, 0, 10), ok_se) == -1
+    assert call_packed(op, bitmap(a, 100, 10, npages=0), bitmap(b, 100, 10, npages=0), ok_se) == -1
+    assert call_packed(op, bitmap(a, 100, 10, off=4), bitmap(b, 100, 10), ok_se) == -1   # misaligned
+    assert call_packed(op, bitmap(a, 100, 11), bitmap(b, 100, 10), ok_se) == -2
+    assert call_packed(op, bitmap(a, 101, 10), bitmap(b, 100, 10), ok_se) == -2
+    assert call_packed(op, bitmap(a, 100, 10, npages=2), bitmap(b, 100, 10), ok_se) == -2
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(a, 100, 10, off=64), ok_se) == -3
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(a, 100, 10), ok_se) == -3
+    big = (300, 3, 150, 1)
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(b, 100, 10), big) == -4
+    need = M.morph_workspace_bytes(op, 0, 100, 10, big)
+    ws = HostBuf(need)
+    assert call_packed(op, bitmap(a, 100, 10), bitmap(b, 100, 10), big, ws.ptr, need - 1) == -4
+    null = M.morph_bitmap_t(None, 100, 10, 2, 1)
+    assert call_packed(op, null, bitmap(b, 100, 10), ok_se) == -1
+
+
+def rle(buf, W, H, cap, npages=1, rp_off=0, runs_off=None):
+    runs_off = (H * npages + 1) * 4 + 64 if runs_off is None else runs_off
+    return M.morph_rle_t(W, H, npages, buf.ptr + rp_off, buf.ptr + runs_off, cap)
+
+
+@pytest.mark.parametrize("op", M.OPS)
+def test_rle_argument_errors(op):
+    f = getattr(M._lib, "morph_%s_rect_rle" % op)
+    a, b = HostBuf(1 << 20), HostBuf(1 << 20)
+    W, H = 200, 30
+    cap = M.morph_rle_max_runs(W, H)
+    se = M.morph_se_t(5, 5, 2, 2)
+    call = lambda d, s, se=se, ws=None, n=0: f(ctypes.byref(d), ctypes.byref(s), se, ws, n, None)
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), M.morph_se_t(5, 5, 5, 2)) == -1
+    assert call(rle(a, W, H, cap), rle(b, W + 1, H, cap)) == -2
+    assert call(rle(a, W, H, cap), rle(a, W, H, cap)) == -3
+    assert call(rle(a, W, H, cap - 1), rle(b, W, H, cap)) == -6
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap)) == -4
+    need = M.morph_rle_workspace_bytes(op, W, H, 1, (5, 5, 2, 2))
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, HostBuf(16).ptr, need - 1) == -4
+    assert call(rle(a, W, H, -1), rle(b, W, H, cap)) == -1
+    # addresses 1 TiB apart, never dereferenced: the size check comes first
+    huge_a = M.morph_rle_t(100000, 60000, 1, 1 << 40, (1 << 40) + (1 << 30), 10**10)
+    huge_b = M.morph_rle_t(100000, 60000, 1, 2 << 40, (2 << 40) + (1 << 30), 10**10)
+    assert call(huge_a, huge_b) == -8
+
+
+def test_conversion_argument_errors():
+    a, b = HostBuf(1 << 16), HostBuf(1 << 16)
+    W, H = 100, 10
+    d = rle(a, W, H, 500)
+    s = bitmap(b, W, H)
+    need = M.morph_pack_to_rle_workspace_bytes(W, H)
+    assert M._lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(s), None, 0, None) == -4
+    assert M._lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(bitmap(b, W + 1, H)), None, 0, None) == -2
+    overlapping = bitmap(a, W, H)
+    assert M._lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(overlapping), HostBuf(need).ptr, need, None) == -3
+    assert M._lib.morph_rle_to_pack(ctypes.byref(bitmap(b, W, H + 1)), ctypes.byref(d), None) == -2
+    assert M._lib.morph_rle_to_pack(ctypes.byref(bitmap(a, W, H)), ctypes.byref(d), None) == -3
+
+
+def test_batch_plan_argument_errors():
+    a, b = HostBuf(1 << 16), HostBuf(1 << 16)
+    h = ctypes.c_void_p()
+    desc = (M.morph_page_desc_t * 1)()
+    desc[0] = M.morph_page_desc_t(bitmap(a, 100, 10), bitmap(b, 100, 10), 7, M.morph_se_t(3, 3, 1, 1), 0, 0)
+    assert M._lib.morph_batch_plan_create(ctypes.byref(h), desc, 1, None) == -1
+    desc[0] = M.morph_page_desc_t(bitmap(a, 100, 10), bitmap(b, 100, 11), 0, M.morph_se_t(3, 3, 1, 1), 0, 0)
+    assert M._lib.morph_batch_plan_create(ctypes.byref(h), desc, 1, None) == -2
+    desc[0] = M.morph_page_desc_t(bitmap(a, 100, 10), bitmap(b, 100, 10), 0, M.morph_se_t(300, 3, 150, 1), 0, 0)
+    assert M._lib.morph_batch_plan_create(ctypes.byref(h), desc, 1, None) == -8
+    assert M._lib.morph_batch_plan_create(None, desc, 1, None) == -1
+    assert M._lib.morph_batch_run(None, 1, None) == -1
