@@ -167,6 +167,18 @@ def main():
     def avg(getter):
         return float(np.mean([getter(e)[0].elapsed_time(getter(e)[1]) for e in evs]))
 
+    # device copy of the same batch: a measured bandwidth ceiling, and the
+    # reference kernel for scaling the HBM byte counters
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(3):
+        c0.record(stream)
+        dst.words.copy_(src.words)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms.append(c0.elapsed_time(c1))
+    copy_gbs = 2 * src.words.numel() * 8 / (min(copy_ms) / 1e3) / 1e9
+
     page_px = W * H
     n_ops = len(packed_jobs)
     px_step = (n_ops * B * page_px if do_packed else 0) + (n_ops * B * page_px if do_rle else 0)
@@ -208,6 +220,7 @@ def main():
                                           for (op, name, _), m in zip(packed_jobs, rle_ms)},
                             "runs_in": int(rle_src.row_ptr[-1].item())}
     out["breakdown"] = breakdown
+    out["copy_ceiling_gbs"] = copy_gbs
 
     # single-page latency of the whole page workload (one page resident)
     if args.only == "all" and args.latency_reps > 0:

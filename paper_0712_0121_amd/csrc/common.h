@@ -12,7 +12,7 @@ namespace morph {
 // ------------------------------------------------------------------ packed
 // Geometry of the fused band kernel (one workgroup = one tile).
 constexpr int kThreads = 512;          // threads per workgroup
-constexpr int kLdsWords = 8192;        // 64 KiB of LDS per workgroup (two per CU)
+constexpr int kLdsWords = 10236;       // ~80 KiB of LDS per workgroup (two per CU, with room for a queue slot)
 constexpr int kChunkMax = 16;          // rows a thread keeps in registers in the column pass
 constexpr int kWordsPerItem = 4;       // consecutive words one row-pass item produces
 constexpr int kItemsMax = 4;           // row-pass items a thread holds across a barrier

@@ -33,6 +33,16 @@ constexpr uint64_t kOnes = ~0ull;
 constexpr int WPT = kWordsPerItem;
 constexpr int CM = kChunkMax;
 
+
+// Workgroup barrier that orders LDS only: global loads and stores in flight
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Low 64 bits of the 128-bit value (hi:lo) shifted right by s, 1 <= s <= 63.
 __device__ __forceinline__ uint64_t funnel_r(uint64_t hi, uint64_t lo, int s)
 {
@@ -86,246 +96,407 @@ __device__ __forceinline__ void row_pass_group(uint64_t (&X)[WPT + 2], int w, in
     if (w >= 128) { row_step<64>(X); m = 128; }
     if (w > m) row_step_rt(X, w - m);
     // origin: out(x) = E_w(x - cx)
+    if (cx == 0) {
 #pragma unroll
-    for (int i = 0; i < WPT; i++)
-        out[i] = (cx == 0) ? X[i + 1] : (cx == 64 ? X[i] : funnel_r(X[i + 1], X[i], 64 - cx));
+        for (int i = 0; i < WPT; i++) out[i] = X[i + 1];
+    } else if (cx == 64) {
+#pragma unroll
+        for (int i = 0; i < WPT; i++) out[i] = X[i];
+    } else {
+        const int sh = 64 - cx;
+#pragma unroll
+        for (int i = 0; i < WPT; i++) out[i] = funnel_r(X[i + 1], X[i], sh);
+    }
+}
+
+// Loads the WPT+2 words c0-1 .. c0+WPT of an LDS row (two words per load
+// when the first is at an even index).
+__device__ __forceinline__ void load_group(const uint64_t *row, int c0, uint64_t (&X)[WPT + 2])
+{
+    if (((c0 - 1) & 1) == 0) {
+        const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(row + c0 - 1);
+#pragma unroll
+        for (int i = 0; i < (WPT + 2) / 2; i++) {
+            const ulonglong2 v = q[i];
+            X[2 * i] = v.x;
+            X[2 * i + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < WPT + 2; i++) X[i] = row[c0 - 1 + i];
+    }
 }
 
 // Column doubling step with a compile-time offset K < CM: partners inside
-// the thread's own run of rows come from registers, the others from LDS,
-// where every thread first publishes the rows its upper neighbour needs.
+// the thread's own run of CM rows come from registers, the others from LDS,
+// where every thread first publishes the K rows its upper neighbour needs.
+// Rows at or past `rows` (the rows the tile allocates in LDS) read as 1.
 template <int K>
-__device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int TW, int NRs,
-                                         int col, int a, int C, bool active)
+__device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int TWp, int rows,
+                                         int col, int a, bool active)
 {
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < (K < CM ? K : CM); i++)
-            if (i < C && a + i < NRs) lds[(a + i) * TW + col] = reg[i];
+        for (int i = 0; i < K; i++) lds[(a + i) * TWp + col] = reg[i];
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int i = 0; i < CM; i++) {
-            if (i < C) {
-                uint64_t p;
-                if (i + K < C) {
-                    p = reg[(i + K < CM) ? i + K : CM - 1];
-                } else {
-                    const int rr = a + i + K;
-                    p = rr < NRs ? lds[rr * TW + col] : kOnes;
-                }
-                reg[i] &= p;
+            uint64_t p;
+            if (i + K < CM) {
+                p = reg[(i + K < CM) ? i + K : CM - 1];
+            } else {
+                const int rr = a + i + K;
+                p = rr < rows ? lds[rr * TWp + col] : kOnes;
             }
+            reg[i] &= p;
         }
     }
 }
 
 // Column step with a run-time offset: every partner comes from LDS.
-__device__ __forceinline__ void col_step_lds(uint64_t *lds, uint64_t (&reg)[CM], int TW, int NRs,
-                                             int col, int a, int C, bool active, int K)
+__device__ __forceinline__ void col_step_lds(uint64_t *lds, uint64_t (&reg)[CM], int TWp, int rows,
+                                             int col, int a, bool active, int K)
 {
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < CM; i++)
-            if (i < C && a + i < NRs) lds[(a + i) * TW + col] = reg[i];
+        for (int i = 0; i < CM; i++) lds[(a + i) * TWp + col] = reg[i];
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int i = 0; i < CM; i++) {
-            if (i < C) {
-                const int rr = a + i + K;
-                reg[i] &= rr < NRs ? lds[rr * TW + col] : kOnes;
-            }
+            const int rr = a + i + K;
+            reg[i] &= rr < rows ? lds[rr * TWp + col] : kOnes;
         }
     }
 }
 
-__device__ __forceinline__ void rect_tile(const RectPage &P, int page, int band, int strip, uint64_t *lds)
+// Geometry of one tile: TR output rows x SW words of one page, plus the rows
+// and words it depends on.
+struct Tile {
+    const uint64_t *src;
+    uint64_t *dst;
+    int y0, TRv, j0, SWv;
+    int TW, TWp;            // LDS row width and pitch (pitch even)
+    int NR;                 // input rows of the first stage
+    int gy0, gj0;           // page row / word of LDS row 0 / column 0
+};
+
+__device__ __forceinline__ Tile make_tile(const RectPage &P, int page, int band, int strip)
+{
+    Tile T;
+    T.src = P.src + (long long)page * P.src_page_words;
+    T.dst = P.dst + (long long)page * P.dst_page_words;
+    T.y0 = band * P.TR;
+    T.TRv = min(P.TR, P.H - T.y0);
+    T.j0 = strip * P.SW;
+    T.SWv = min(P.SW, P.nw - T.j0);
+    T.TW = T.SWv + 2 * P.nst;
+    T.TWp = T.TW + (T.TW & 1);
+    int hsum = P.st[0].h - 1, top = P.st[0].cy;
+    if (P.nst == 2) { hsum += P.st[1].h - 1; top += P.st[1].cy; }
+    T.NR = T.TRv + hsum;
+    T.gy0 = T.y0 - top;
+    T.gj0 = T.j0 - P.nst;
+    return T;
+}
+
+// Issues the global loads of a tile's first column pass into reg: thread
+// (chunk, col) gets rows chunk*CM .. chunk*CM+CM-1 of LDS column col.
+// Words outside the page get the value that the input transform of
+// take_loads turns into all ones.
+__device__ __forceinline__ void issue_loads(const RectPage &P, const Tile &T, uint64_t (&reg)[CM])
 {
     const int tid = threadIdx.x;
-    const uint64_t *src = P.src + (long long)page * P.src_page_words;
-    uint64_t *dst = P.dst + (long long)page * P.dst_page_words;
-    const int nst = P.nst;
-    const int y0 = band * P.TR;
-    const int TRv = min(P.TR, P.H - y0);
-    const int j0 = strip * P.SW;
-    const int SWv = min(P.SW, P.nw - j0);
-    const int TW = SWv + 2 * nst;
-    int hsum = P.st[0].h - 1, top = P.st[0].cy;
-    if (nst == 2) { hsum += P.st[1].h - 1; top += P.st[1].cy; }
-    int NRs = TRv + hsum;           // rows held in LDS for the current stage
-    int gy0 = y0 - top;             // page row of LDS row 0
-    const int gj0 = j0 - nst;       // page word of LDS column 0
-
-    // ---- stage the input rows; outside the page every pixel is 1
-    {
-        const int total = NRs * TW;
-        int r = tid / TW, c = tid - (tid / TW) * TW;
-        const int dr = kThreads / TW, dc = kThreads - (kThreads / TW) * TW;
-        for (int q = tid; q < total; q += kThreads) {
-            const int gy = gy0 + r, gj = gj0 + c;
-            uint64_t v = kOnes;
-            if (gy >= 0 && gy < P.H && gj >= 0 && gj < P.nw) {
-                v = src[(long long)gy * P.sstride + gj];
-                if (P.in_c) v = ~v;
-                if (gj == P.nw - 1) v |= ~P.padmask;
-            }
-            lds[q] = v;
-            r += dr;
-            c += dc;
-            if (c >= TW) { c -= TW; r++; }
+    const int chunk = tid / T.TW, col = tid - (tid / T.TW) * T.TW;
+    const int chunks = (T.NR + CM - 1) / CM;
+    const int a = chunk * CM;
+    const int gj = T.gj0 + col;
+    const bool colin = chunk < chunks && gj >= 0 && gj < P.nw;
+    const uint64_t fill = P.in_c ? 0ull : kOnes;
+    const uint64_t *p = T.src + (long long)(T.gy0 + a) * P.sstride + gj;
+    const bool interior = T.gy0 >= 0 && T.gy0 + T.NR <= P.H;
+    if (interior) {
+#pragma unroll
+        for (int i = 0; i < CM; i++) {
+            reg[i] = (colin && a + i < T.NR) ? *p : fill;
+            p += P.sstride;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < CM; i++) {
+            const int gy = T.gy0 + a + i;
+            reg[i] = (colin && a + i < T.NR && gy >= 0 && gy < P.H) ? *p : fill;
+            p += P.sstride;
         }
     }
-    __syncthreads();
+}
 
+// Completes the loads: optional complement, pad bits of the last word set.
+__device__ __forceinline__ void take_loads(const RectPage &P, const Tile &T, uint64_t (&reg)[CM])
+{
+    const int tid = threadIdx.x;
+    const int col = tid - (tid / T.TW) * T.TW;
+    const uint64_t inv = P.in_c ? kOnes : 0ull;
+    const uint64_t pad = (T.gj0 + col == P.nw - 1) ? ~P.padmask : 0ull;
+#pragma unroll
+    for (int i = 0; i < CM; i++) reg[i] = (reg[i] ^ inv) | pad;
+}
+
+
+// Runs every stage of one tile.  reg holds the tile's first-stage loads
+// (issued, not yet waited for).  Before the last row pass, which needs only
+// LDS, the loads of the next tile are issued into reg, so they are in flight
+// while this tile finishes.
+template <class GetNext>
+__device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, uint64_t (&reg)[CM],
+                                             uint64_t *lds, GetNext get_next)
+{
+    bool more = false;
+    const int tid = threadIdx.x;
+    const int nst = P.nst;
+    int NRs = T.NR;
+    int gy0 = T.gy0;
+    const int TWp = T.TWp;
     for (int s = 0; s < nst; s++) {
         const Stage S = (s == 0) ? P.st[0] : P.st[1];
-        const int c_lo = 1 + s, c_hi = TW - 1 - s;
+        const bool last = s + 1 == nst;
 
-        // ---- row pass, in place on columns [c_lo, c_hi)
-        if (S.w > 1) {
-            const int G = (c_hi - c_lo + WPT - 1) / WPT;
-            const int items = NRs * G;
-            const int dr = kThreads / G, dg = kThreads - (kThreads / G) * G;
+        // ---- column pass (first: the order is free by separability)
+        const int c_lo = s, ncols = T.TW - 2 * s;
+        const int chunks = (NRs + CM - 1) / CM;
+        const int rows = chunks * CM;
+        const int chunk = tid / ncols;
+        const int col = c_lo + (tid - chunk * ncols);
+        const bool active = chunk < chunks;
+        const int a = chunk * CM;
+        if (s == 0) {
+            take_loads(P, T, reg);
+        } else {
+#pragma unroll
+            for (int i = 0; i < CM; i++) reg[i] = active ? lds[(a + i) * TWp + col] : kOnes;
+        }
+        const int h = S.h;
+        int m = 1;
+        if (h >= 2)  { col_step<1>(lds, reg, TWp, rows, col, a, active);  m = 2; }
+        if (h >= 4)  { col_step<2>(lds, reg, TWp, rows, col, a, active);  m = 4; }
+        if (h >= 8)  { col_step<4>(lds, reg, TWp, rows, col, a, active);  m = 8; }
+        if (h >= 16) { col_step<8>(lds, reg, TWp, rows, col, a, active);  m = 16; }
+        if (h >= 32) { col_step<16>(lds, reg, TWp, rows, col, a, active); m = 32; }
+        while (2 * m <= h) {
+            col_step_lds(lds, reg, TWp, rows, col, a, active, m);
+            m *= 2;
+        }
+        if (h > m) col_step_lds(lds, reg, TWp, rows, col, a, active, h - m);
+        const int NRo = NRs - (h - 1);  // rows of this stage's output
+        const int gyo = gy0 + S.cy;     // page row of output row 0
+        if (h > 1) lds_barrier();       // partners read: LDS free for the results
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < CM; i++) lds[(a + i) * TWp + col] = reg[i];
+        }
+        lds_barrier();
+
+        // ---- row pass on rows [0, NRo): output columns [c_lo+1, TW-1-s)
+        const int o_lo = c_lo + 1, o_hi = T.TW - 1 - s;
+        const int G = (o_hi - o_lo + WPT - 1) / WPT;
+        const int items = NRo * G;
+        const int dr = kThreads / G, dg = kThreads - (kThreads / G) * G;
+        if (last) {
+            more = get_next(reg);           // issues the next tile's loads into reg
+            const uint64_t inv = P.out_c ? kOnes : 0ull;
+            int r = tid / G, g = tid - (tid / G) * G;
+            for (int q = tid; q < items; q += kThreads) {
+                const int c0 = o_lo + g * WPT;
+                uint64_t X[WPT + 2];
+                load_group(lds + r * TWp, c0, X);
+                uint64_t o[WPT];
+                if (S.w > 1) {
+                    row_pass_group(X, S.w, S.cx, o);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < WPT; i++) o[i] = X[i + 1];
+                }
+                const int gj = T.gj0 + c0;
+#pragma unroll
+                for (int i = 0; i < WPT; i++) o[i] ^= inv;
+                if (gj + WPT > P.nw - 1 && gj <= P.nw - 1) {
+#pragma unroll
+                    for (int i = 0; i < WPT; i++)
+                        if (gj + i == P.nw - 1) o[i] &= P.padmask;
+                }
+                uint64_t *out = T.dst + (long long)(gyo + r) * P.dstride + gj;
+                if (c0 + WPT <= o_hi && (((uintptr_t)out) & 15) == 0) {
+                    ulonglong2 *o2 = reinterpret_cast<ulonglong2 *>(out);
+#pragma unroll
+                    for (int i = 0; i < WPT / 2; i++) o2[i] = make_ulonglong2(o[2 * i], o[2 * i + 1]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < WPT; i++)
+                        if (c0 + i < o_hi) out[i] = o[i];
+                }
+                r += dr;
+                g += dg;
+                if (g >= G) { g -= G; r++; }
+            }
+        } else {
+            // intermediate: computed into registers, then written back in
+            // place, (complemented,) clipped to the page with outside = 1
             uint64_t res[kItemsMax][WPT];
             int r = tid / G, g = tid - (tid / G) * G;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
                 if (tid + k * kThreads < items) {
-                    const int c0 = c_lo + g * WPT;
+                    const int c0 = o_lo + g * WPT;
                     uint64_t X[WPT + 2];
+                    load_group(lds + r * TWp, c0, X);
+                    if (S.w > 1) {
+                        row_pass_group(X, S.w, S.cx, res[k]);
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < WPT + 2; i++) {
-                        const int c = c0 - 1 + i;
-                        X[i] = c < TW ? lds[r * TW + c] : kOnes;
+                        for (int i = 0; i < WPT; i++) res[k][i] = X[i + 1];
                     }
-                    row_pass_group(X, S.w, S.cx, res[k]);
                 }
                 r += dr;
                 g += dg;
                 if (g >= G) { g -= G; r++; }
             }
-            __syncthreads();
+            lds_barrier();
             r = tid / G;
             g = tid - (tid / G) * G;
+            const uint64_t minv = P.mid_c ? kOnes : 0ull;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
                 if (tid + k * kThreads < items) {
-                    const int c0 = c_lo + g * WPT;
+                    const int c0 = o_lo + g * WPT;
+                    const int gy = gyo + r;
+                    const bool rowin = gy >= 0 && gy < P.H;
 #pragma unroll
-                    for (int i = 0; i < WPT; i++)
-                        if (c0 + i < c_hi) lds[r * TW + c0 + i] = res[k][i];
+                    for (int i = 0; i < WPT; i++) {
+                        const int c = c0 + i, gj = T.gj0 + c;
+                        if (c < o_hi) {
+                            uint64_t v = res[k][i] ^ minv;
+                            if (!rowin || gj < 0 || gj >= P.nw) v = kOnes;
+                            else if (gj == P.nw - 1) v |= ~P.padmask;
+                            lds[r * TWp + c] = v;
+                        }
+                    }
                 }
                 r += dr;
                 g += dg;
                 if (g >= G) { g -= G; r++; }
             }
-            __syncthreads();
-        }
-
-        // ---- column pass on columns [c_lo, c_hi)
-        const int ncols = c_hi - c_lo;
-        const int chunks = kThreads / ncols;
-        const int C = (NRs + chunks - 1) / chunks;
-        const int chunk = tid / ncols;
-        const int col = c_lo + (tid - chunk * ncols);
-        const bool active = chunk < chunks;
-        const int a = chunk * C;
-        uint64_t reg[CM];
-#pragma unroll
-        for (int i = 0; i < CM; i++)
-            reg[i] = (active && i < C && a + i < NRs) ? lds[(a + i) * TW + col] : kOnes;
-
-        const int h = S.h;
-        int m = 1;
-        if (h >= 2)  { col_step<1>(lds, reg, TW, NRs, col, a, C, active);  m = 2; }
-        if (h >= 4)  { col_step<2>(lds, reg, TW, NRs, col, a, C, active);  m = 4; }
-        if (h >= 8)  { col_step<4>(lds, reg, TW, NRs, col, a, C, active);  m = 8; }
-        if (h >= 16) { col_step<8>(lds, reg, TW, NRs, col, a, C, active);  m = 16; }
-        if (h >= 32) { col_step<16>(lds, reg, TW, NRs, col, a, C, active); m = 32; }
-        while (2 * m <= h) {
-            col_step_lds(lds, reg, TW, NRs, col, a, C, active, m);
-            m *= 2;
-        }
-        if (h > m) col_step_lds(lds, reg, TW, NRs, col, a, C, active, h - m);
-
-        // reg[i] now holds the erosion of row a+i of this stage's output
-        const int NRo = NRs - (h - 1);
-        const int gyo = gy0 + S.cy;           // page row of output row 0
-        if (s + 1 < nst) {
-            // intermediate: (optionally complemented), clipped to the page,
-            // outside = 1 for the next erosion
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int i = 0; i < CM; i++) {
-                    const int r = a + i;
-                    if (i < C && r < NRo) {
-                        const int gy = gyo + r, gj = gj0 + col;
-                        uint64_t v = P.mid_c ? ~reg[i] : reg[i];
-                        if (gy < 0 || gy >= P.H || gj < 0 || gj >= P.nw) v = kOnes;
-                        else if (gj == P.nw - 1) v |= ~P.padmask;
-                        lds[r * TW + col] = v;
-                    }
-                }
-            }
-            __syncthreads();
+            lds_barrier();
             NRs = NRo;
             gy0 = gyo;
-        } else if (active) {
-            const int gj = gj0 + col;
-#pragma unroll
-            for (int i = 0; i < CM; i++) {
-                const int r = a + i;
-                if (i < C && r < NRo) {
-                    uint64_t v = P.out_c ? ~reg[i] : reg[i];
-                    if (gj == P.nw - 1) v &= P.padmask;
-                    dst[(long long)(gyo + r) * P.dstride + gj] = v;
-                }
-            }
         }
+    }
+    return more;
+}
+
+// Tiles of a launch are numbered page-major, then band, then strip.  Each XCD
+// (workgroups are dealt round-robin over the 8 XCDs) takes a contiguous range
+// of tiles, so neighbouring tiles share halo rows in one L2.
+__device__ __forceinline__ void tile_coords(const RectPage &P, int t, int &page, int &band, int &strip)
+{
+    const int per_page = P.nbands * P.nstrips;
+    page = t / per_page;
+    const int u = t - page * per_page;
+    band = u / P.nstrips;
+    strip = u - band * P.nstrips;
+}
+
+// One operation over all tiles of npages pages: a persistent grid, each
+// workgroup taking every nx-th tile of its XCD's range.  Tile coordinates
+// advance by carries, without divisions in the loop.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void rect_kernel(RectPage Parg,
+                                                                                              int ntiles)
+{
+    __shared__ __align__(16) uint64_t lds[kLdsWords];
+    // the page parameters are read from the argument segment where they are
+    // used, rather than all held in scalar registers for the whole kernel
+    (void)Parg;
+    const RectPage &P = *(const RectPage *)__builtin_amdgcn_kernarg_segment_ptr();
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b & 7, nx = (G - x + 7) >> 3;
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    const int start = x * q + min(x, rem), count = q + (x < rem ? 1 : 0);
+    int k = b >> 3;
+    if (k >= count) return;
+    const int nb = P.nbands, ns = P.nstrips;
+    // step nx tiles = dp pages, db bands, ds strips (with carries)
+    const int per_page = nb * ns;
+    const int dp = nx / per_page, du = nx - dp * per_page;
+    const int db = du / ns, ds = du - db * ns;
+    int page, band, strip;
+    tile_coords(P, start + k, page, band, strip);
+    uint64_t reg[CM];
+    issue_loads(P, make_tile(P, page, band, strip), reg);
+    for (;;) {
+        int np = page + dp, nbd = band + db, nst = strip + ds;
+        if (nst >= ns) { nst -= ns; nbd++; }
+        if (nbd >= nb) { nbd -= nb; np++; }
+        const bool has = k + nx < count;
+        auto get_next = [&](uint64_t (&r)[CM]) {
+            if (!has) return false;
+            issue_loads(P, make_tile(P, np, nbd, nst), r);
+            return true;
+        };
+        if (!process_tile(P, make_tile(P, page, band, strip), reg, lds, get_next)) break;
+        k += nx;
+        page = np;
+        band = nbd;
+        strip = nst;
+        lds_barrier();
     }
 }
 
-// Tiles of a launch are numbered band-major; hand consecutive tiles to the
-// same XCD (workgroups are dealt round-robin over the 8 XCDs) so a tile and
-// its neighbour share halo rows in one L2.
-__device__ __forceinline__ int xcd_tile(int b, int T)
+// A batch of pages with their own operations: workgroups take tiles from a
+// shared queue (largest pages first), claiming the next tile early so its
+// loads can be issued before the current tile ends.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void rect_batch_kernel(
+    const RectPage *__restrict__ pages, const TileRef *__restrict__ tiles, int ntiles, int *queue)
 {
-    const int q = T >> 3, rem = T & 7;
-    const int x = b & 7, k = b >> 3;
-    return x * q + min(x, rem) + k;
-}
-
-__global__ __launch_bounds__(kThreads) void rect_kernel(RectPage P)
-{
-    __shared__ uint64_t lds[kLdsWords];
-    const int T = P.nbands * P.nstrips;
-    const int t = xcd_tile((int)blockIdx.x, T);
-    const int band = t / P.nstrips;
-    rect_tile(P, (int)blockIdx.y, band, t - band * P.nstrips, lds);
-}
-
-__global__ __launch_bounds__(kThreads) void rect_batch_kernel(const RectPage *__restrict__ pages,
-                                                             const TileRef *__restrict__ tiles,
-                                                             int ntiles, int *queue)
-{
-    __shared__ uint64_t lds[kLdsWords];
-    __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-        __syncthreads();
-        const int t = next;
-        __syncthreads();
-        if (t >= ntiles) break;                 // every wave sees the same t
+    __shared__ __align__(16) uint64_t lds[kLdsWords];
+    __shared__ int slot[2];
+    if (threadIdx.x == 0) slot[0] = atomicAdd(queue, 1);
+    __syncthreads();
+    int t = __builtin_amdgcn_readfirstlane(slot[0]);
+    if (t >= ntiles) return;                       // every wave sees the same t
+    uint64_t reg[CM];
+    {
         const TileRef tr = tiles[t];
-        const RectPage P = pages[tr.page];
-        rect_tile(P, 0, tr.band, tr.strip, lds);
-        __syncthreads();
+        const RectPage &P = pages[__builtin_amdgcn_readfirstlane(tr.page)];
+        issue_loads(P, make_tile(P, 0, __builtin_amdgcn_readfirstlane(tr.band),
+                                 __builtin_amdgcn_readfirstlane(tr.strip)), reg);
+    }
+    int parity = 1;
+    for (;;) {
+        // claim the next tile now; it is read after this tile's first barrier
+        if (threadIdx.x == 0) slot[parity] = atomicAdd(queue, 1);
+        const int par = parity;
+        int tn = ntiles;
+        auto get_next = [&](uint64_t (&r)[CM]) {
+            tn = __builtin_amdgcn_readfirstlane(slot[par]);
+            if (tn >= ntiles) return false;
+            const TileRef r2 = tiles[tn];
+            const RectPage &Pn = pages[__builtin_amdgcn_readfirstlane(r2.page)];
+            issue_loads(Pn, make_tile(Pn, 0, __builtin_amdgcn_readfirstlane(r2.band),
+                                      __builtin_amdgcn_readfirstlane(r2.strip)), r);
+            return true;
+        };
+        const TileRef tr = tiles[t];
+        const RectPage &P = pages[__builtin_amdgcn_readfirstlane(tr.page)];
+        const Tile T = make_tile(P, 0, __builtin_amdgcn_readfirstlane(tr.band),
+                                 __builtin_amdgcn_readfirstlane(tr.strip));
+        if (!process_tile(P, T, reg, lds, get_next)) break;
+        t = tn;
+        parity ^= 1;
+        lds_barrier();
     }
 }
 
@@ -351,23 +522,28 @@ int device_cu_count()
     return cached_cu_count;
 }
 
-// Largest number of LDS rows (input rows of stage 0) a tile of width TW can
-// hold for page p, or 0 if none.
+// Largest number of rows (input rows of the first stage) a tile of width TW
+// can hold for page p, or 0 if none: the LDS array (rows are allocated in
+// runs of kChunkMax, pitch rounded up to even, 8 words of slack), the
+// column runs (one thread per run, so runs per column <= threads / columns),
+// and the row-pass results a thread holds across a barrier in every stage
+// but the last.
 static int max_rows(const RectPage &p, int TW)
 {
-    int nr = kLdsWords / TW;
-    int drop = 0;                   // rows lost before stage s
+    const int TWp = TW + (TW & 1);
+    int nr = ((kLdsWords - 8) / TWp) / kChunkMax * kChunkMax;
+    int drop = 0;                   // rows consumed before stage s
     for (int s = 0; s < p.nst; s++) {
-        const int ncols = TW - 2 - 2 * s;
-        if (ncols < 1) return 0;
+        const int ncols = TW - 2 * s;
+        if (ncols < 3) return 0;
         const int chunks = kThreads / ncols;
         if (chunks < 1) return 0;
         nr = std::min(nr, chunks * kChunkMax + drop);
-        if (p.st[s].w > 1) {
-            const int G = (ncols + WPT - 1) / WPT;
+        drop += p.st[s].h - 1;
+        if (s + 1 < p.nst) {
+            const int G = (ncols - 2 + WPT - 1) / WPT;
             nr = std::min(nr, (kThreads * kItemsMax) / G + drop);
         }
-        drop += p.st[s].h - 1;
     }
     return nr;
 }
@@ -432,26 +608,30 @@ bool tile_fits(const RectPage &p)
         hsum += S.h - 1;
     }
     const int TW = p.SW + 2 * p.nst;
+    const int TWp = TW + (TW & 1);
     int NRs = p.TR + hsum;
-    if ((long long)NRs * TW > kLdsWords) return false;
+    const int rows0 = (NRs + kChunkMax - 1) / kChunkMax * kChunkMax;
+    if ((long long)rows0 * TWp + 8 > kLdsWords) return false;
     for (int s = 0; s < p.nst; s++) {
-        const int ncols = TW - 2 - 2 * s;
-        const int chunks = kThreads / ncols;
-        if (ncols < 1 || chunks < 1 || (NRs + chunks - 1) / chunks > kChunkMax) return false;
-        if (p.st[s].w > 1 && (long long)NRs * ((ncols + WPT - 1) / WPT) > (long long)kThreads * kItemsMax)
-            return false;
+        const int ncols = TW - 2 * s;
+        if (ncols < 3) return false;
+        if ((NRs + kChunkMax - 1) / kChunkMax > kThreads / ncols) return false;
         NRs -= p.st[s].h - 1;
+        if (NRs < 1) return false;
+        if (s + 1 < p.nst &&
+            (long long)NRs * ((ncols - 2 + WPT - 1) / WPT) > (long long)kThreads * kItemsMax)
+            return false;
     }
     return true;
 }
 
 hipError_t launch_rect(const RectPage &p, int npages, hipStream_t stream)
 {
-    const long long T = (long long)p.nbands * p.nstrips;
-    if (T <= 0 || npages <= 0) return hipSuccess;
-    if (!tile_fits(p) || T > 0x7fffffffLL || npages > 65535) return hipErrorInvalidValue;
-    dim3 grid((unsigned)T, (unsigned)npages);
-    hipLaunchKernelGGL(rect_kernel, grid, dim3(kThreads), 0, stream, p);
+    const long long T = (long long)p.nbands * p.nstrips * npages;
+    if (T <= 0) return hipSuccess;
+    if (!tile_fits(p) || T > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int grid = (int)std::min<long long>(T, 2LL * device_cu_count());
+    hipLaunchKernelGGL(rect_kernel, dim3(grid), dim3(kThreads), 0, stream, p, (int)T);
     return hipGetLastError();
 }
 
