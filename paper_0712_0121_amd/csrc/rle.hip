@@ -213,163 +213,257 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
     words[(long long)page * page_words + (long long)y * stride + j] = v;
 }
 
-// ------------------------------------------------------ within-line pass
-// One wave per row, lanes over runs.  Erosion by a 1 x w element with
-// origin cx: [s, e) -> [s + cx, e - (w-1-cx)), a side on the row border
-// stays where it is (outside pixels are 1), and empty runs are dropped.
-// Dilation: [s, e) -> [s - cx, e + w-1-cx) clipped to [0, W), and runs that
-// overlap or touch are merged.
-template <bool EMIT, bool DILATE>
-__global__ __launch_bounds__(64 * kRowWaves) void row_pass_kernel(
-    const int *__restrict__ in_rp, const int *__restrict__ in_runs, long long in_cap, int R, int W,
-    int w, int cx, int *__restrict__ counts, const int *__restrict__ out_rp,
-    int *__restrict__ out_runs, long long out_cap)
+// ------------------------------------------------- rows in two layouts
+// Between passes the library keeps run-length rows in a slot layout: row r
+// owns runs r*cap .. r*cap+cap-1 and cnt[r] of them are used, cap being the
+// most runs a row of the image width can have.  A pass can then write its
+// rows without knowing where earlier rows end, so no scan is needed until
+// the final result is packed into CSR form.
+struct RowsIn {
+    const int *rp;          // CSR offsets, or nullptr for the slot layout
+    const int *cnt;         // slot layout: runs per row
+    const int *runs;
+    long long cap;          // CSR: runs the array holds; slot: runs per row
+};
+
+__device__ __forceinline__ void row_span(const RowsIn &v, long long r, long long &base, int &n)
 {
-    const int r = blockIdx.x * kRowWaves + (int)(threadIdx.x >> 6);
-    if (r >= R) return;
-    const int lane = lane_id();
-    // a malformed row_ptr cannot send reads past the input's capacity
-    const int b0 = (int)min((long long)max(in_rp[r], 0), in_cap);
-    const int n = (int)max(0LL, min((long long)in_rp[r + 1], in_cap) - b0);
-    const int left = DILATE ? cx : -cx;                 // start moves to s - left
-    const int right = DILATE ? (w - 1 - cx) : -(w - 1 - cx);
-    const unsigned long long lt = (1ull << lane) - 1;
-    long long obase = EMIT ? out_rp[r] : 0;
-    int carry = 0;
-    for (int k0 = 0; k0 < n; k0 += 64) {
-        const int k = k0 + lane;
-        const bool valid = k < n;
-        int s = 0, e = 0;
-        if (valid) {
-            s = in_runs[2 * (b0 + k)];
-            e = in_runs[2 * (b0 + k) + 1];
-        }
-        int ns, ne;
-        if (DILATE) {
-            ns = max(0, s - left);
-            ne = min(W, e + right);
-        } else {
-            ns = (s == 0) ? 0 : s - left;
-            ne = (e == W) ? W : e + right;
-        }
-        bool first, last;
-        if (DILATE) {
-            // a run starts a group unless it meets the previous run's grown end
-            int pe = -1;
-            if (valid && k > 0) pe = min(W, in_runs[2 * (b0 + k - 1) + 1] + right);
-            first = valid && (k == 0 || ns > pe);
-            last = valid && (k == n - 1 || max(0, in_runs[2 * (b0 + k + 1)] - left) > ne);
-        } else {
-            first = last = valid && ns < ne;
-        }
-        const unsigned long long fm = __ballot(first);
-        const int idx = carry + __popcll(fm & lt);
-        if (EMIT) {
-            const long long o = obase + idx;
-            if (first && o < out_cap) out_runs[2 * o] = ns;
-            const long long oe = o - (first ? 0 : 1);
-            if (last && oe >= 0 && oe < out_cap) out_runs[2 * oe + 1] = ne;
-        }
-        carry += __popcll(fm);
+    if (v.rp) {
+        base = min((long long)max(v.rp[r], 0), v.cap);
+        n = (int)max(0LL, min((long long)v.rp[r + 1], v.cap) - base);
+    } else {
+        base = r * v.cap;
+        n = min(max(v.cnt[r], 0), (int)v.cap);
     }
-    if (!EMIT && lane == 0) counts[r] = carry;
+}
+
+constexpr int kGroup = 16;                        // lanes that share one row
+constexpr int kGroupsPerBlock = 256 / kGroup;
+
+__device__ __forceinline__ int glane() { return (int)(threadIdx.x & (kGroup - 1)); }
+
+// This group's 16 bits of a wave-wide ballot.
+__device__ __forceinline__ unsigned group_ballot(bool p)
+{
+    const unsigned long long m = __ballot(p);
+    return (unsigned)(m >> (lane_id() & ~(kGroup - 1))) & 0xffffu;
+}
+
+__device__ __forceinline__ int group_incl_scan(int x)
+{
+    const int gl = glane();
+#pragma unroll
+    for (int d = 1; d < kGroup; d <<= 1) {
+        const int t = __shfl_up(x, d, kGroup);
+        if (gl >= d) x += t;
+    }
+    return x;
+}
+
+// ------------------------------------------------------ within-line pass
+// Erosion of every row by a 1 x w element with origin cx (section "Within-
+// Line Morphological Operations"): run [s, e) becomes [s + cx, e - (w-1-cx)),
+// a side lying on the row border stays put (outside pixels are 1), and runs
+// that vanish are dropped.  With comp_in the rows' complements are eroded:
+// the gaps between runs, including the ones at both ends, play the runs.
+// One group of 16 lanes per row, lanes over runs, compaction by ballot.
+__global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W, int w, int cx, int comp_in,
+                                                        int *__restrict__ out_cnt,
+                                                        int *__restrict__ out_runs, long long cap_row)
+{
+    const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (r >= R) return;                    // whole group
+    const int gl = glane();
+    long long base;
+    int n;
+    row_span(in, r, base, n);
+    const int *rr = in.runs + 2 * base;
+    const int ncand = comp_in ? n + 1 : n;
+    const int right = w - 1 - cx;
+    int *o = out_runs + 2 * r * cap_row;
+    int carry = 0;
+    for (int k0 = 0; k0 < ncand; k0 += kGroup) {
+        const int k = k0 + gl;
+        int s = 0, e = 0;
+        if (k < ncand) {
+            if (comp_in) {
+                s = (k == 0) ? 0 : rr[2 * k - 1];
+                e = (k == n) ? W : rr[2 * k];
+            } else {
+                s = rr[2 * k];
+                e = rr[2 * k + 1];
+            }
+        }
+        const int ns = (s == 0) ? 0 : s + cx;
+        const int ne = (e == W) ? W : e - right;
+        const bool keep = k < ncand && s < e && ns < ne;
+        const unsigned gm = group_ballot(keep);
+        const int idx = carry + __popc(gm & ((1u << gl) - 1));
+        if (keep && idx < cap_row) {
+            o[2 * idx] = ns;
+            o[2 * idx + 1] = ne;
+        }
+        carry += __popc(gm);
+    }
+    if (gl == 0) out_cnt[r] = (int)min((long long)carry, cap_row);
 }
 
 // ----------------------------------------------------- between-line pass
-// A view of a run-length image with virtual rows: row r of page p is real
-// row r - off of that page if it lies in [0, real), otherwise it is the
-// full row [0, W) (erosion) or the empty row (dilation).
-struct RowView {
-    const int *rp;
-    const int *runs;
-    long long cap;            // runs the runs array holds
-    int off, real, rows;      // rows = rows per page seen through the view
-};
+constexpr int kStageInts = 512;             // LDS ints per group for the two rows of a step
 
-struct Row {
-    const int *runs;
-    int n;
-    bool full;
-};
-
-__device__ __forceinline__ Row view_row(const RowView &v, int page, int r, bool erode)
+// Orders a wave's LDS accesses (all lanes of a group are in one wave).
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const int rr = r - v.off;
-    Row o;
-    if (rr >= 0 && rr < v.real) {
-        const int i = page * v.real + rr;
-        const long long b = min((long long)max(v.rp[i], 0), v.cap);
-        o.runs = v.runs + 2 * b;
-        o.n = (int)max(0LL, min((long long)v.rp[i + 1], v.cap) - b);
-        o.full = false;
-    } else {
-        o.runs = nullptr;
-        o.n = erode ? 1 : 0;
-        o.full = true;
-    }
-    return o;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-__device__ __forceinline__ void run_at(const Row &r, int k, int W, int &s, int &e)
+// Intersection of run lists A (na runs) and B (nb runs) into o, by the
+// lanes of one group: lane k takes runs k, k+16, ... of A, finds the first
+// run of B that ends after it starts, and emits every overlap in order.
+__device__ __forceinline__ int group_intersect(const int *A, int na, const int *B, int nb, int *o,
+                                               long long cap_row)
 {
-    if (r.full) { s = 0; e = W; }
-    else { s = r.runs[2 * k]; e = r.runs[2 * k + 1]; }
-}
-
-// One thread per output row: out[r] = A[r] AND A[r+K] (erosion) or
-// A[r] OR A[r+K] (dilation), as an ordered merge of the two run lists.
-template <bool EMIT, bool ERODE>
-__global__ __launch_bounds__(256) void col_stage_kernel(RowView A, int K, int P, int W,
-                                                        int *__restrict__ counts,
-                                                        const int *__restrict__ out_rp,
-                                                        int *__restrict__ out_runs, long long out_cap)
-{
-    const int NB = A.rows - K;
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (long long)P * NB) return;
-    const int page = (int)(t / NB), r = (int)(t - (long long)page * NB);
-    const Row a = view_row(A, page, r, ERODE), b = view_row(A, page, r + K, ERODE);
-    long long o = EMIT ? out_rp[t] : 0;
-    int cnt = 0;
-    int i = 0, j = 0;
-    if (ERODE) {
-        while (i < a.n && j < b.n) {
-            int as, ae, bs, be;
-            run_at(a, i, W, as, ae);
-            run_at(b, j, W, bs, be);
-            const int s = max(as, bs), e = min(ae, be);
-            if (s < e) {
-                if (EMIT) { if (o < out_cap) { out_runs[2 * o] = s; out_runs[2 * o + 1] = e; } o++; }
-                cnt++;
+    const int gl = glane();
+    int carry = 0;
+    for (int k0 = 0; k0 < na; k0 += kGroup) {
+        const int k = k0 + gl;
+        int c = 0, j0 = 0, sa = 0, ea = 0;
+        if (k < na) {
+            sa = A[2 * k];
+            ea = A[2 * k + 1];
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (B[2 * mid + 1] > sa) hi = mid; else lo = mid + 1;
             }
-            if (ae <= be) i++;
-            if (be <= ae) j++;
+            j0 = lo;
+            for (int j = j0; j < nb && B[2 * j] < ea; j++) c++;
         }
-    } else {
-        int cs = 0, ce = -1;               // current merged run, none yet
-        while (i < a.n || j < b.n) {
-            int s, e;
-            int as = 0x7fffffff, ae = 0, bs = 0x7fffffff, be = 0;
-            if (i < a.n) run_at(a, i, W, as, ae);
-            if (j < b.n) run_at(b, j, W, bs, be);
-            if (as <= bs) { s = as; e = ae; i++; } else { s = bs; e = be; j++; }
-            if (ce >= 0 && s <= ce) {
-                ce = max(ce, e);
-            } else {
-                if (ce >= 0) {
-                    if (EMIT) { if (o < out_cap) { out_runs[2 * o] = cs; out_runs[2 * o + 1] = ce; } o++; }
-                    cnt++;
+        const int inc = group_incl_scan(c);
+        long long idx = carry + inc - c;
+        if (k < na) {
+            for (int j = j0; j < nb && B[2 * j] < ea; j++) {
+                if (idx < cap_row) {
+                    o[2 * idx] = max(sa, B[2 * j]);
+                    o[2 * idx + 1] = min(ea, B[2 * j + 1]);
                 }
-                cs = s;
-                ce = e;
+                idx++;
             }
         }
-        if (ce >= 0) {
-            if (EMIT) { if (o < out_cap) { out_runs[2 * o] = cs; out_runs[2 * o + 1] = ce; } o++; }
-            cnt++;
+        carry += __shfl(inc, kGroup - 1, kGroup);
+    }
+    return carry;
+}
+
+// One doubling step between lines (sections "Between Line Boolean
+// Operations" and "Efficient Binary Decompositions"): output row r of a page
+// is the intersection of rows r and r + K of the input, where input row x is
+// stored row x - off if that lies in [0, real), and otherwise a full row
+// [0, W) (outside the image erosion sees 1s).  NA rows per page come in,
+// NA - K go out.  One group of lanes per output row; both rows are first
+// copied to LDS when they fit, so the searches run there.
+__global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, int P,
+                                                      int W, int *__restrict__ out_cnt,
+                                                      int *__restrict__ out_runs, long long cap_row)
+{
+    __shared__ int stage[kGroupsPerBlock][kStageInts];
+    const int NB = NA - K;
+    const long long t = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (t >= (long long)P * NB) return;     // whole group
+    const int gl = glane();
+    const int page = (int)(t / NB), r = (int)(t - (long long)page * NB);
+    const int ia = r - off, ib = r + K - off;
+    const bool va = ia >= 0 && ia < real, vb = ib >= 0 && ib < real;
+    int *o = out_runs + 2 * t * cap_row;
+    if (!va && !vb) {
+        if (gl == 0) {
+            o[0] = 0;
+            o[1] = W;
+            out_cnt[t] = 1;
+        }
+        return;
+    }
+    if (!va || !vb) {                       // full row AND x = x
+        long long base;
+        int n;
+        row_span(in, (long long)page * real + (va ? ia : ib), base, n);
+        n = (int)min((long long)n, cap_row);
+        const int *src = in.runs + 2 * base;
+        for (int k = gl; k < n; k += kGroup) {
+            o[2 * k] = src[2 * k];
+            o[2 * k + 1] = src[2 * k + 1];
+        }
+        if (gl == 0) out_cnt[t] = n;
+        return;
+    }
+    long long ba, bb;
+    int na, nb;
+    row_span(in, (long long)page * real + ia, ba, na);
+    row_span(in, (long long)page * real + ib, bb, nb);
+    const int *A = in.runs + 2 * ba;
+    const int *B = in.runs + 2 * bb;
+    int cnt;
+    if (2 * (na + nb) <= kStageInts) {
+        int *sm = stage[threadIdx.x >> 4];
+        for (int k = gl; k < 2 * na; k += kGroup) sm[k] = A[k];
+        for (int k = gl; k < 2 * nb; k += kGroup) sm[2 * na + k] = B[k];
+        wave_lds_sync();
+        cnt = group_intersect(sm, na, sm + 2 * na, nb, o, cap_row);
+    } else {
+        cnt = group_intersect(A, na, B, nb, o, cap_row);
+    }
+    if (gl == 0) out_cnt[t] = (int)min((long long)cnt, cap_row);
+}
+
+// ---------------------------------------------------------- final packing
+// Runs per row of the complement of slot rows: the gaps, without an empty
+// first or last one.
+__global__ __launch_bounds__(256) void gap_count_kernel(RowsIn in, int R, int W, int *__restrict__ counts)
+{
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    long long base;
+    int n;
+    row_span(in, r, base, n);
+    const int *rr = in.runs + 2 * base;
+    int g = n + 1;
+    if (n > 0 && rr[0] == 0) g--;
+    if (n > 0 && rr[2 * n - 1] == W) g--;
+    counts[r] = g;
+}
+
+// Copies slot rows (or their complements) to CSR rows at row_ptr.
+__global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W, int comp,
+                                                        const int *__restrict__ row_ptr,
+                                                        int *__restrict__ out_runs, long long cap)
+{
+    const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (r >= R) return;
+    const int gl = glane();
+    long long base;
+    int n;
+    row_span(in, r, base, n);
+    const int *rr = in.runs + 2 * base;
+    const long long o = row_ptr[r];
+    const int nout = row_ptr[r + 1] - row_ptr[r];
+    const int skip = (comp && n > 0 && rr[0] == 0) ? 1 : 0;
+    for (int k = gl; k < nout; k += kGroup) {
+        int s, e;
+        if (comp) {
+            const int g = k + skip;
+            s = (g == 0) ? 0 : rr[2 * g - 1];
+            e = (g == n) ? W : rr[2 * g];
+        } else {
+            s = rr[2 * k];
+            e = rr[2 * k + 1];
+        }
+        if (o + k < cap) {
+            out_runs[2 * (o + k)] = s;
+            out_runs[2 * (o + k) + 1] = e;
         }
     }
-    if (!EMIT) counts[t] = cnt;
 }
 
 // Canonical-form check: sets *bad when a row breaks it.
@@ -443,146 +537,129 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
     return hipGetLastError();
 }
 
-// Workspace layout of a run-length rectangle operation on P pages of H rows:
-//   counts[P*(H+h-1)] | scan tmp | T0 (row pass out) | T1, T2 (stages) | T3 (open/close middle)
+// Workspace of a run-length rectangle operation on P pages of H rows: two
+// slot buffers (counts + runs) for every row the passes produce, the counts
+// of the final rows, and scan scratch.
 struct RleWs {
-    int *counts, *tmp;
-    int *rp[4];
-    int *runs[4];
+    int *cnt[2];
+    int *runs[2];
+    int *fcount;
+    int *tmp;
+    long long rows_max, cap_row;
     size_t bytes;
 };
 
-static RleWs rle_layout(void *base, int op, int32_t W, int32_t rows, int32_t H, morph_se_t se)
+static RleWs rle_layout(void *base, int32_t W, int32_t rows, int32_t H, morph_se_t se)
 {
-    const int P = rows / H;
-    const long long ext = (long long)P * (H + se.h - 1);
-    const long long half = (W + 1) / 2;
+    const long long P = rows / H;
     RleWs L{};
+    L.rows_max = P * (H + (long long)se.h - 1);
+    L.cap_row = (W + 1) / 2;
     char *p = (char *)base;
     size_t off = 0;
-    auto take = [&](size_t b) { char *q = p ? p + off : nullptr; off += r256(b); return (int *)q; };
-    L.counts = take((size_t)ext * 4);
-    L.tmp = take(scan_workspace(ext));
-    const long long rows_of[4] = {(long long)P * H, ext, ext, (long long)P * H};
-    const int nbuf = (op == MORPH_OPEN || op == MORPH_CLOSE) ? 4 : 3;
-    for (int i = 0; i < 4; i++) {
-        if (i < nbuf) {
-            L.rp[i] = take((size_t)(rows_of[i] + 1) * 4);
-            L.runs[i] = take((size_t)rows_of[i] * half * 8);
-        } else {
-            L.rp[i] = nullptr;
-            L.runs[i] = nullptr;
-        }
+    auto take = [&](size_t b) { int *q = p ? (int *)(p + off) : nullptr; off += r256(b); return q; };
+    for (int i = 0; i < 2; i++) {
+        L.cnt[i] = take((size_t)L.rows_max * 4);
+        L.runs[i] = take((size_t)L.rows_max * L.cap_row * 8);
     }
+    L.fcount = take((size_t)P * H * 4);
+    L.tmp = take(scan_workspace(P * H));
     L.bytes = off;
     return L;
 }
 
 size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t se)
 {
-    return rle_layout(nullptr, op, W, rows, H, se).bytes;
+    (void)op;
+    return rle_layout(nullptr, W, rows, H, se).bytes;
 }
 
-// One erosion or dilation of P pages: src (CSR) -> dst (CSR).
-static hipError_t rle_erode_dilate(bool erode, const int *src_rp, const int *src_runs,
-                                   long long src_cap, int *dst_rp, int *dst_runs, long long dst_cap,
-                                   int P, int W, int H, morph_se_t se, const RleWs &L, hipStream_t s)
+static RowsIn slot_rows(const RleWs &L, int i)
+{
+    return RowsIn{nullptr, L.cnt[i], L.runs[i], L.cap_row};
+}
+
+// Erosion of P pages (or of their complements, comp_in) by the rectangle
+// (w, h, cx, cy): the within-line pass into slot buffer `to`, then the
+// doubling steps between lines, alternating buffers.  Returns the buffer
+// that holds the P*H result rows.
+static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w, int h, int cx, int cy,
+                       const RleWs &L, int to, hipStream_t s, hipError_t *err)
 {
     const int R = P * H;
-    const long long half = (W + 1) / 2;
-    const unsigned g = blocks_for(R, kRowWaves);
-    // within-line pass; skipped when the element is one pixel wide, unless
-    // nothing else runs (then it copies src to dst)
-    const bool rowpass = se.w > 1 || se.h == 1;
-    const int *cur_rp = src_rp, *cur_runs = src_runs;
-    long long cur_cap = src_cap;
-    if (rowpass) {
-        int *o_rp = se.h == 1 ? dst_rp : L.rp[0];
-        int *o_runs = se.h == 1 ? dst_runs : L.runs[0];
-        const long long o_cap = se.h == 1 ? dst_cap : (long long)R * half;
-        if (erode) {
-            hipLaunchKernelGGL((row_pass_kernel<false, false>), dim3(g), dim3(64 * kRowWaves), 0, s, src_rp,
-                               src_runs, src_cap, R, W, se.w, se.cx, L.counts, nullptr, nullptr, 0LL);
-        } else {
-            hipLaunchKernelGGL((row_pass_kernel<false, true>), dim3(g), dim3(64 * kRowWaves), 0, s, src_rp,
-                               src_runs, src_cap, R, W, se.w, se.cx, L.counts, nullptr, nullptr, 0LL);
-        }
-        hipError_t e = exclusive_scan(L.counts, R, o_rp, L.tmp, s);
-        if (e != hipSuccess) return e;
-        if (erode) {
-            hipLaunchKernelGGL((row_pass_kernel<true, false>), dim3(g), dim3(64 * kRowWaves), 0, s, src_rp,
-                               src_runs, src_cap, R, W, se.w, se.cx, nullptr, o_rp, o_runs, o_cap);
-        } else {
-            hipLaunchKernelGGL((row_pass_kernel<true, true>), dim3(g), dim3(64 * kRowWaves), 0, s, src_rp,
-                               src_runs, src_cap, R, W, se.w, se.cx, nullptr, o_rp, o_runs, o_cap);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        cur_rp = o_rp;
-        cur_runs = o_runs;
-        cur_cap = o_cap;
-    }
-    if (se.h == 1) return hipSuccess;
-    // between-line pass: rows of the extended page are r = 0 .. H+h-2, row r
-    // being image row r - top (top = cy for erosion, h-1-cy for dilation)
-    const int top = erode ? se.cy : se.h - 1 - se.cy;
-    RowView v{cur_rp, cur_runs, cur_cap, top, H, H + se.h - 1};
-    // offsets: 1, 2, 4, ... while doubling stays <= h, then h - m
-    int offs[40], nst = 0;
+    hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
+                       cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row);
+    int cur = to;
+    // rows of the extended page: 0 .. H+h-2, row x being image row x - cy
+    int off = cy, real = H, NA = H + h - 1;
     int m = 1;
-    while (2 * m <= se.h) { offs[nst++] = m; m *= 2; }
-    if (se.h > m) offs[nst++] = se.h - m;
-    int ping = 1;
-    for (int k = 0; k < nst; k++) {
-        const int K = offs[k];
-        const int NB = v.rows - K;
-        const bool lastst = k + 1 == nst;
-        int *o_rp = lastst ? dst_rp : L.rp[ping];
-        int *o_runs = lastst ? dst_runs : L.runs[ping];
-        const long long n = (long long)P * NB;
-        const long long o_cap = lastst ? dst_cap : n * half;
-        const unsigned gb = blocks_for(n, 256);
-        if (erode)
-            hipLaunchKernelGGL((col_stage_kernel<false, true>), dim3(gb), dim3(256), 0, s, v, K, P, W,
-                               L.counts, nullptr, nullptr, 0LL);
-        else
-            hipLaunchKernelGGL((col_stage_kernel<false, false>), dim3(gb), dim3(256), 0, s, v, K, P, W,
-                               L.counts, nullptr, nullptr, 0LL);
-        hipError_t e = exclusive_scan(L.counts, (int)n, o_rp, L.tmp, s);
-        if (e != hipSuccess) return e;
-        if (erode)
-            hipLaunchKernelGGL((col_stage_kernel<true, true>), dim3(gb), dim3(256), 0, s, v, K, P, W,
-                               nullptr, o_rp, o_runs, o_cap);
-        else
-            hipLaunchKernelGGL((col_stage_kernel<true, false>), dim3(gb), dim3(256), 0, s, v, K, P, W,
-                               nullptr, o_rp, o_runs, o_cap);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        v = RowView{o_rp, o_runs, o_cap, 0, NB, NB};
-        ping = 3 - ping;
+    int offs[40], n = 0;
+    while (2 * m <= h) { offs[n++] = m; m *= 2; }
+    if (h > m) offs[n++] = h - m;
+    for (int k = 0; k < n; k++) {
+        const int K = offs[k], NB = NA - K;
+        const int nxt = 1 - cur;
+        hipLaunchKernelGGL(col_and_kernel, dim3(blocks_for((long long)P * NB, kGroupsPerBlock)), dim3(256), 0, s,
+                           slot_rows(L, cur), off, real, NA, K, P, W, L.cnt[nxt], L.runs[nxt],
+                           (long long)L.cap_row);
+        cur = nxt;
+        off = 0;
+        real = NB;
+        NA = NB;
     }
-    return hipSuccess;
+    *err = hipGetLastError();
+    return cur;
 }
 
+// Packs the P*H slot rows of buffer b (complemented when comp) into dst.
+static hipError_t finish(const RleWs &L, int b, int comp, const morph_rle_t &dst, int W, hipStream_t s)
+{
+    const int R = dst.height * dst.npages;
+    const int *counts = L.cnt[b];
+    if (comp) {
+        hipLaunchKernelGGL(gap_count_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, s, slot_rows(L, b), R, W,
+                           L.fcount);
+        counts = L.fcount;
+    }
+    hipError_t e = exclusive_scan(counts, R, dst.row_ptr, L.tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pack_rows_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, slot_rows(L, b), R,
+                       W, comp, dst.row_ptr, dst.runs, (long long)dst.capacity);
+    return hipGetLastError();
+}
+
+// erode:  E_B(A)
+// dilate: not E_B^(not A)             (dilation by complementation)
+// open:   not E_B^(not E_B(A))
+// close:  E_B(not E_B^(not A))
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t s)
 {
     (void)ws_bytes;
     const int P = src.npages, H = src.height, W = src.width;
-    const RleWs L = rle_layout(ws, op, W, P * H, H, se);
+    const RleWs L = rle_layout(ws, W, P * H, H, se);
+    const RowsIn in{src.row_ptr, nullptr, src.runs, (long long)src.capacity};
+    const int w = se.w, h = se.h, cx = se.cx, cy = se.cy;
+    const int rx = w - 1 - cx, ry = h - 1 - cy;
+    hipError_t e = hipSuccess;
+    int b;
     switch (op) {
     case MORPH_ERODE:
+        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
+        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s);
     case MORPH_DILATE:
-        return rle_erode_dilate(op == MORPH_ERODE, src.row_ptr, src.runs, src.capacity, dst.row_ptr,
-                                dst.runs, dst.capacity, P, W, H, se, L, s);
+        b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e);
+        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s);
     case MORPH_OPEN:
-    case MORPH_CLOSE: {
-        const bool e1 = op == MORPH_OPEN;
-        const long long mid_cap = (long long)P * H * ((W + 1) / 2);
-        hipError_t e = rle_erode_dilate(e1, src.row_ptr, src.runs, src.capacity, L.rp[3], L.runs[3],
-                                        mid_cap, P, W, H, se, L, s);
+        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
         if (e != hipSuccess) return e;
-        return rle_erode_dilate(!e1, L.rp[3], L.runs[3], mid_cap, dst.row_ptr, dst.runs, dst.capacity,
-                                P, W, H, se, L, s);
-    }
+        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, rx, ry, L, 1 - b, s, &e);
+        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s);
+    case MORPH_CLOSE:
+        b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e);
+        if (e != hipSuccess) return e;
+        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, cx, cy, L, 1 - b, s, &e);
+        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s);
     }
     return hipErrorInvalidValue;
 }
