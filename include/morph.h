@@ -218,6 +218,22 @@ int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t 
 int64_t morph_batch_tiles(const morph_batch_plan_t *plan);
 void morph_batch_plan_destroy(morph_batch_plan_t *plan);
 
+/*
+ * The same persistent launch without a plan, for batches that change from
+ * call to call (a serving loop): the tile tables are built on the host and
+ * copied into the caller's device workspace `ws` (256-byte aligned, at least
+ * morph_batch_workspace_bytes(descs, n) bytes) before the launch, all on
+ * `stream`.  host_staging, if not NULL, is caller-owned pinned host memory of
+ * the same size that the copy reads from asynchronously: it must stay
+ * untouched until the stream has passed this call.  With host_staging NULL
+ * the tables are copied from library memory and the call waits for the copy.
+ * Returns -1 from morph_batch_workspace_bytes for descriptors the batch
+ * kernel cannot take (see morph_batch_plan_create).
+ */
+int64_t morph_batch_workspace_bytes(const morph_page_desc_t *descs, int32_t n);
+int morph_batch_launch(const morph_page_desc_t *descs, int32_t n, void *ws, size_t ws_bytes,
+                       void *host_staging, size_t staging_bytes, morph_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

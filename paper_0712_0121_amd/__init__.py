@@ -33,7 +33,8 @@ __all__ = [
     "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
-    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan",
+    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes",
+    "morph_batch_launch",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack",
 ]
 
@@ -91,6 +92,8 @@ def _load():
         "morph_batch_run": (ctypes.c_int, [P, I32, P]),
         "morph_batch_tiles": (I64, [P]),
         "morph_batch_plan_destroy": (None, [P]),
+        "morph_batch_workspace_bytes": (I64, [ctypes.POINTER(morph_page_desc_t), I32]),
+        "morph_batch_launch": (ctypes.c_int, [ctypes.POINTER(morph_page_desc_t), I32, P, SZ, P, SZ, P]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -355,6 +358,38 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def _descs(items):
+    items = list(items)
+    arr = (morph_page_desc_t * max(1, len(items)))()
+    for i, it in enumerate(items):
+        dst, src, op, s = it[:4]
+        tr, sw = (it[4], it[5]) if len(it) >= 6 else (0, 0)
+        arr[i] = morph_page_desc_t(dst.struct(), src.struct(), OPS.index(op) if isinstance(op, str) else op,
+                                   _se(s), int(tr), int(sw))
+    return arr, len(items)
+
+
+def morph_batch_workspace_bytes(items) -> int:
+    """Bytes of device workspace (and pinned staging) morph_batch_launch
+    needs for these (dst, src, op, se[, tile_rows, strip_words]) items; -1 if
+    the batch kernel cannot take one of them."""
+    arr, n = _descs(items)
+    return int(_lib.morph_batch_workspace_bytes(arr, n))
+
+
+def morph_batch_launch(items, ws, staging=None, stream=None):
+    """One persistent launch over the items (see morph_batch_launch in
+    include/morph.h); ws: device uint8 tensor; staging: pinned host uint8
+    tensor or None."""
+    arr, n = _descs(items)
+    p, nb = _ws(ws)
+    if staging is not None:
+        sp, sn = ctypes.c_void_p(staging.data_ptr()), staging.numel()
+    else:
+        sp, sn = None, 0
+    _check(_lib.morph_batch_launch(arr, n, p, nb, sp, sn, _stream(stream)), "morph_batch_launch")
 
 
 # ------------------------------------------------------------- conveniences

@@ -254,14 +254,20 @@ size_t morph_workspace_bytes(int op, int repr, int32_t width, int32_t height, mo
 }
 
 // ---- batch plans
-int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *descs, int32_t n,
-                            morph_stream_t stream)
+}  // extern "C"
+
+namespace morph {
+
+// Plans a batch: one fused launch per page, tiles ordered with the most
+// expensive pages first (their tiles leave the queue first) and each page's
+// tiles in band order so neighbours run close together in time.
+static int build_batch(const morph_page_desc_t *descs, int32_t n, std::vector<RectPage> &pages,
+                       std::vector<TileRef> &tiles)
 {
-    (void)stream;
-    if (!plan || (!descs && n > 0) || n < 0) return MORPH_E_INVAL;
-    *plan = nullptr;
-    std::vector<RectPage> pages;
+    if ((!descs && n > 0) || n < 0) return MORPH_E_INVAL;
     std::vector<double> cost;
+    pages.clear();
+    tiles.clear();
     for (int i = 0; i < n; i++) {
         const morph_page_desc_t &d = descs[i];
         if (!bitmap_ok(&d.dst) || !bitmap_ok(&d.src) || !se_ok(d.se) || d.op < MORPH_ERODE ||
@@ -290,17 +296,36 @@ int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *
         }
         cost.push_back((double)p.nw * (p.H + hs * p.nbands) * lg);
     }
-    // expensive pages first (their tiles leave the queue first), each page's
-    // tiles in band order so neighbours run close together in time
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<TileRef> tiles;
     for (int i : order)
         for (int b = 0; b < pages[i].nbands; b++)
             for (int s = 0; s < pages[i].nstrips; s++) tiles.push_back(TileRef{i, b, s, 0});
     if (tiles.size() > 0x7fffffff) return MORPH_E_UNSUPPORTED;
+    return MORPH_OK;
+}
 
+// Device layout of an uploaded batch: queue counter, page table, tile list.
+static size_t batch_bytes(size_t npages, size_t ntiles)
+{
+    return 256 + round256(npages * sizeof(RectPage)) + round256(ntiles * sizeof(TileRef));
+}
+
+}  // namespace morph
+
+extern "C" {
+
+int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *descs, int32_t n,
+                            morph_stream_t stream)
+{
+    (void)stream;
+    if (!plan) return MORPH_E_INVAL;
+    *plan = nullptr;
+    std::vector<RectPage> pages;
+    std::vector<TileRef> tiles;
+    const int rc = build_batch(descs, n, pages, tiles);
+    if (rc != MORPH_OK) return rc;
     morph_batch_plan_t *pl = new (std::nothrow) morph_batch_plan_t();
     if (!pl) return MORPH_E_HIP;
     hipError_t e = hipSuccess;
@@ -321,6 +346,52 @@ int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *
     pl->ntiles = (int)tiles.size();
     pl->nblocks = std::max(1, std::min(pl->ntiles, 2 * device_cu_count()));
     *plan = pl;
+    return MORPH_OK;
+}
+
+int64_t morph_batch_workspace_bytes(const morph_page_desc_t *descs, int32_t n)
+{
+    std::vector<RectPage> pages;
+    std::vector<TileRef> tiles;
+    if (build_batch(descs, n, pages, tiles) != MORPH_OK) return -1;
+    return (int64_t)batch_bytes(pages.size(), tiles.size());
+}
+
+int morph_batch_launch(const morph_page_desc_t *descs, int32_t n, void *ws, size_t ws_bytes,
+                       void *host_staging, size_t staging_bytes, morph_stream_t stream)
+{
+    std::vector<RectPage> pages;
+    std::vector<TileRef> tiles;
+    const int rc = build_batch(descs, n, pages, tiles);
+    if (rc != MORPH_OK) return rc;
+    if (tiles.empty()) return MORPH_OK;
+    const size_t need = batch_bytes(pages.size(), tiles.size());
+    if (!ws || ws_bytes < need || (((uintptr_t)ws) & 255)) return MORPH_E_WORKSPACE;
+    if (host_staging && staging_bytes < need) return MORPH_E_WORKSPACE;
+    // table image: [256 bytes: counter] [pages] [tiles]
+    const size_t po = 256, to = 256 + round256(pages.size() * sizeof(RectPage));
+    std::vector<char> local;
+    char *img;
+    if (host_staging) {
+        img = (char *)host_staging;
+    } else {
+        local.resize(need);
+        img = local.data();
+    }
+    std::memcpy(img + po, pages.data(), pages.size() * sizeof(RectPage));
+    std::memcpy(img + to, tiles.data(), tiles.size() * sizeof(TileRef));
+    hipStream_t s = (hipStream_t)stream;
+    char *d = (char *)ws;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d + po, img + po, need - po, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (!host_staging && (e = hipStreamSynchronize(s)) != hipSuccess) ||
+        (e = launch_reset_counter((int *)d, s)) != hipSuccess ||
+        (e = launch_rect_batch((const RectPage *)(d + po), (const TileRef *)(d + to), (int)tiles.size(),
+                               (int *)d, std::max(1, std::min((int)tiles.size(), 2 * device_cu_count())), s)) !=
+            hipSuccess) {
+        set_hip_error(e);
+        return MORPH_E_HIP;
+    }
     return MORPH_OK;
 }
 

@@ -1,0 +1,347 @@
+"""Serving loop: continuous batching of page requests with chains of
+rectangle operations on one GPU.
+
+Requests arrive with a packed page (host memory) and a chain of operations,
+e.g. close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5.  The server
+
+* admits requests first come first served while the device bytes they need
+  (two resident page buffers each) fit in an HBM budget; a request larger
+  than the whole budget is rejected, others wait;
+* uploads admitted pages on a copy stream, so uploads overlap the kernels;
+* every scheduling step runs the next operation of every admitted request
+  that is not already on the device as ONE persistent batched launch
+  (morph_batch_launch), so requests at different points of their chains,
+  and requests that arrived while others were running, share launches;
+  the page stays resident between its operations (two buffers, swapped);
+* downloads finished pages on the copy stream and frees their budget.
+
+The scheduler only talks to an executor object, so its logic can be tested
+without a GPU.  GpuExecutor is the product executor; PlainRunner is the
+comparison: one page at a time, upload, each elementary operation as its own
+launch, download.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+# chain of the serving workload: (op, (w, h)) with h x w element strings
+# close 1x41, open 3x3, dilate 15x5, erode 15x5
+SERVE_CHAIN = (("close", (41, 1)), ("open", (3, 3)), ("dilate", (5, 15)), ("erode", (5, 15)))
+
+
+def centred(w, h):
+    return (w, h, w // 2, h // 2)
+
+
+def chain_ses(chain):
+    return [(op, centred(*wh)) if len(wh) == 2 else (op, tuple(wh)) for op, wh in chain]
+
+
+@dataclasses.dataclass(eq=False)
+class Request:
+    rid: int
+    W: int
+    H: int
+    words: object                  # host (rows, stride) words: numpy uint64 or pinned torch int64
+    chain: list                    # [(op, (w, h, cx, cy)), ...]
+    arrival: float = 0.0           # seconds on the server clock
+    pos: int = 0                   # operations done
+    busy: bool = False             # an operation is on the device
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    result: object = None
+    error: str | None = None
+    state: dict = dataclasses.field(default_factory=dict)   # executor-private
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class Server:
+    """Admission under a byte budget plus continuous batching (see module
+    docstring).  Call submit() as requests arrive and step() in a loop."""
+
+    def __init__(self, executor, budget_bytes: int, max_inflight_batches: int = 2,
+                 clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_batches = max_inflight_batches
+        self.clock = clock
+        self.t0 = clock()
+        self.used = 0
+        self.pending = collections.deque()
+        self.active = []
+        self.batches = collections.deque()     # (token, [requests])
+        self.downloading = []
+        self.completed = []
+        self.failed = []
+        self.launches = 0
+        self.peak_used = 0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def submit(self, req: Request, arrival: float | None = None):
+        req.arrival = self.now() if arrival is None else arrival
+        if self.ex.footprint(req) > self.budget:
+            req.error = "request needs %d bytes, budget is %d" % (self.ex.footprint(req), self.budget)
+            req.t_done = self.now()
+            self.failed.append(req)
+            return
+        self.pending.append(req)
+
+    def _fail(self, reqs, msg):
+        for r in reqs:
+            r.error = msg
+            r.t_done = self.now()
+            r.busy = False
+            if r in self.active:
+                self.active.remove(r)
+            self.used -= self.ex.footprint(r)
+            self.ex.release(r)
+            self.failed.append(r)
+
+    def step(self) -> bool:
+        """One scheduling step; returns True if anything happened."""
+        moved = False
+        # finished launches: advance their requests
+        while self.batches and self.ex.done(self.batches[0][0]):
+            token, reqs = self.batches.popleft()
+            err = self.ex.error(token)
+            if err:
+                self._fail(reqs, err)
+                moved = True
+                continue
+            for r in reqs:
+                self.ex.advance(r)
+                r.pos += 1
+                r.busy = False
+                if r.pos == len(r.chain):
+                    self.active.remove(r)
+                    self.ex.begin_download(r)
+                    self.downloading.append(r)
+            moved = True
+        # finished downloads
+        still = []
+        for r in self.downloading:
+            if self.ex.downloaded(r):
+                r.result = self.ex.finish(r)
+                r.t_done = self.now()
+                self.ex.release(r)
+                self.used -= self.ex.footprint(r)
+                self.completed.append(r)
+                moved = True
+            else:
+                still.append(r)
+        self.downloading = still
+        # admission, first come first served
+        while self.pending and self.used + self.ex.footprint(self.pending[0]) <= self.budget:
+            r = self.pending.popleft()
+            self.used += self.ex.footprint(r)
+            self.peak_used = max(self.peak_used, self.used)
+            r.t_admit = self.now()
+            self.ex.begin(r)
+            self.active.append(r)
+            moved = True
+        # next operation of every idle admitted request, as one launch
+        if len(self.batches) < self.max_batches:
+            ready = [r for r in self.active if not r.busy and r.pos < len(r.chain)]
+            if ready:
+                try:
+                    token = self.ex.launch(ready)
+                except Exception as e:          # the launch could not be queued
+                    self._fail(ready, "launch failed: %s" % e)
+                    return True
+                for r in ready:
+                    r.busy = True
+                self.batches.append((token, ready))
+                self.launches += 1
+                moved = True
+        return moved
+
+    def idle(self) -> bool:
+        return not (self.pending or self.active or self.batches or self.downloading)
+
+    def drain(self, timeout: float = 60.0):
+        end = self.clock() + timeout
+        while not self.idle():
+            if not self.step():
+                time.sleep(20e-6)
+            if self.clock() > end:
+                raise TimeoutError("server did not drain")
+
+
+class GpuExecutor:
+    """Runs the server's work on the GPU through the C ABI."""
+
+    def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4):
+        import torch
+        import paper_0712_0121_amd as M
+        self.M, self.torch = M, torch
+        self.device = torch.device(device)
+        self.compute = torch.cuda.Stream(device=self.device)
+        self.copy = torch.cuda.Stream(device=self.device)
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.staging = [torch.empty(ws_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(staging_slots)]
+        self.staging_ev = [None] * staging_slots
+        self.slot = 0
+
+    def footprint(self, r: Request) -> int:
+        return 2 * r.H * ((r.W + 63) // 64) * 8
+
+    def begin(self, r: Request):
+        torch, M = self.torch, self.M
+        host = r.words
+        if not isinstance(host, torch.Tensor):
+            host = torch.from_numpy(np.ascontiguousarray(host).view(np.int64))
+        a = M.Bitmap.empty(r.W, r.H, device=self.device)
+        b = M.Bitmap.empty(r.W, r.H, device=self.device)
+        for t in (a.words, b.words):           # used on both side streams
+            t.record_stream(self.copy)
+            t.record_stream(self.compute)
+        with torch.cuda.stream(self.copy):
+            a.words.copy_(host[:, : a.stride], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        r.state = {"cur": a, "nxt": b, "up": ev, "host": host}
+
+    def launch(self, reqs):
+        torch, M = self.torch, self.M
+        items = []
+        for r in reqs:
+            st = r.state
+            if st.get("up") is not None:
+                self.compute.wait_event(st["up"])
+                st["up"] = None
+            op, se = r.chain[r.pos]
+            items.append((st["nxt"], st["cur"], op, se))
+        k = self.slot
+        self.slot = (k + 1) % len(self.staging)
+        if self.staging_ev[k] is not None:
+            self.staging_ev[k].synchronize()       # its copy has been consumed
+        M.morph_batch_launch(items, self.ws, self.staging[k], stream=self.compute)
+        ev = torch.cuda.Event()
+        ev.record(self.compute)
+        self.staging_ev[k] = ev
+        for r in reqs:
+            r.state["ev"] = ev
+        return ev
+
+    def done(self, token) -> bool:
+        return token.query()
+
+    def error(self, token):
+        return None
+
+    def advance(self, r: Request):
+        st = r.state
+        st["cur"], st["nxt"] = st["nxt"], st["cur"]
+
+    def begin_download(self, r: Request):
+        torch = self.torch
+        st = r.state
+        out = torch.empty((r.H, st["cur"].stride), dtype=torch.int64, pin_memory=True)
+        with torch.cuda.stream(self.copy):
+            self.copy.wait_event(st["ev"])
+            out.copy_(st["cur"].words, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        st["out"], st["down"] = out, ev
+
+    def downloaded(self, r: Request) -> bool:
+        return r.state["down"].query()
+
+    def finish(self, r: Request):
+        return r.state["out"].numpy().view(np.uint64)
+
+    def release(self, r: Request):
+        r.state = {}
+
+
+class PlainRunner:
+    """The comparison path: one page at a time, upload, each elementary
+    operation (opening and closing split into erosion and dilation) as its
+    own launch, download, then the next page."""
+
+    def __init__(self, device="cuda:0"):
+        import torch
+        import paper_0712_0121_amd as M
+        self.M, self.torch = M, torch
+        self.device = torch.device(device)
+
+    @staticmethod
+    def elementary(chain):
+        out = []
+        for op, se in chain:
+            if op == "open":
+                out += [("erode", se), ("dilate", se)]
+            elif op == "close":
+                out += [("dilate", se), ("erode", se)]
+            else:
+                out.append((op, se))
+        return out
+
+    def run_one(self, r: Request):
+        torch, M = self.torch, self.M
+        host = r.words
+        if not isinstance(host, torch.Tensor):
+            host = torch.from_numpy(np.ascontiguousarray(host).view(np.int64))
+        a = M.Bitmap.empty(r.W, r.H, device=self.device)
+        b = M.Bitmap.empty(r.W, r.H, device=self.device)
+        a.words.copy_(host[:, : a.stride], non_blocking=True)
+        for op, se in self.elementary(r.chain):
+            M.PACKED[op](b, a, se)
+            a, b = b, a
+        out = torch.empty((r.H, a.stride), dtype=torch.int64, pin_memory=True)
+        out.copy_(a.words, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        return out.numpy().view(np.uint64)
+
+
+def run_trace_served(server: Server, requests, arrivals, timeout=120.0):
+    """Submits requests[i] at arrivals[i] seconds (server clock) and runs the
+    scheduler until all are done."""
+    order = np.argsort(arrivals, kind="stable")
+    i = 0
+    end = server.clock() + timeout
+    while i < len(order) or not server.idle():
+        now = server.now()
+        while i < len(order) and arrivals[order[i]] <= now:
+            server.submit(requests[order[i]], arrival=float(arrivals[order[i]]))
+            i += 1
+        if not server.step():
+            time.sleep(10e-6)
+        if server.clock() > end:
+            raise TimeoutError("trace did not finish")
+    return server.completed
+
+
+def run_trace_plain(runner: PlainRunner, requests, arrivals, clock=time.perf_counter):
+    """Serves the same trace with the plain path: requests in arrival order,
+    each started when it has arrived and the previous one is done."""
+    t0 = clock()
+    order = np.argsort(arrivals, kind="stable")
+    for k in order:
+        r = requests[k]
+        r.arrival = float(arrivals[k])
+        while clock() - t0 < r.arrival:
+            time.sleep(10e-6)
+        r.result = runner.run_one(r)
+        r.t_done = clock() - t0
+    return [requests[k] for k in order]
+
+
+def latency_stats(done, t_first=None):
+    lat = np.array([r.latency for r in done])
+    if len(lat) == 0:
+        return {"n": 0}
+    t_first = min(r.arrival for r in done) if t_first is None else t_first
+    span = max(r.t_done for r in done) - t_first
+    return {"n": int(len(lat)), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "pages_per_s": float(len(lat) / span) if span > 0 else None}

@@ -1,0 +1,75 @@
+"""The served form on the GPU: every request's result is the same whether it
+is served alone or in a mix with others (arriving while others run, sharing
+launches), equals the plain per-page path, and equals the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pagegen
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    require_gpu()
+
+
+def make_requests(n, seed=5):
+    from paper_0712_0121_amd.serve import Request, SERVE_CHAIN, chain_ses
+    sizes = [(300, 211), (640, 97), (1275, 1650), (130, 40), (2550, 3300)]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W, H = sizes[i % len(sizes)]
+        if W >= 1275:
+            img = pagegen.text_page(7000 + i, W, H).img
+        else:
+            img = (rng.random((H, W)) < 0.25).astype(np.uint8)
+        words = torch.from_numpy(oracle.pack(img).view(np.int64)).pin_memory()
+        out.append(Request(i, W, H, words, chain_ses(SERVE_CHAIN)))
+    return out
+
+
+def expected(r):
+    img = oracle.unpack(r.words.numpy().view(np.uint64), r.W)
+    for op, se in r.chain:
+        img = oracle.sat_apply(op, img, se)
+    return oracle.pack(img)
+
+
+def served(reqs, arrivals, budget=64 << 30):
+    from paper_0712_0121_amd.serve import GpuExecutor, Server, run_trace_served
+    s = Server(GpuExecutor(), budget_bytes=budget)
+    run_trace_served(s, reqs, arrivals, timeout=60)
+    assert not s.failed, [r.error for r in s.failed]
+    return s
+
+
+def test_mix_equals_alone_equals_plain_equals_oracle():
+    from paper_0712_0121_amd.serve import PlainRunner
+    reqs = make_requests(20)
+    arrivals = np.cumsum(np.random.default_rng(1).exponential(0.002, len(reqs)))
+    s = served(reqs, arrivals)
+    assert len(s.completed) == len(reqs)
+    assert s.launches < 4 * len(reqs)           # operations shared launches
+    mix = {r.rid: r.result.copy() for r in reqs}
+    for r in make_requests(20):
+        s1 = served([r], np.zeros(1))
+        np.testing.assert_array_equal(r.result, mix[r.rid], err_msg="request %d alone vs mix" % r.rid)
+    plain = PlainRunner()
+    for r in make_requests(20)[:6]:
+        np.testing.assert_array_equal(plain.run_one(r), mix[r.rid])
+    for r in reqs:
+        np.testing.assert_array_equal(mix[r.rid], expected(r), err_msg="request %d vs oracle" % r.rid)
+
+
+def test_small_budget_serves_everything():
+    reqs = make_requests(8)
+    fp = max(2 * r.H * ((r.W + 63) // 64) * 8 for r in reqs)
+    s = served(reqs, np.zeros(len(reqs)), budget=fp + 1)
+    assert s.peak_used <= fp + 1
+    for r in reqs:
+        np.testing.assert_array_equal(r.result, expected(r))

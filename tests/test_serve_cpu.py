@@ -1,0 +1,150 @@
+"""The serving scheduler on the CPU, with a mock executor that runs each
+operation with the oracle and finishes work only after a few polls (so
+requests overlap as they would on the device)."""
+import numpy as np
+import pytest
+
+import oracle
+import pagegen
+from paper_0712_0121_amd.serve import Request, Server, SERVE_CHAIN, chain_ses
+
+
+class Token:
+    def __init__(self, polls, err=None):
+        self.left = polls
+        self.err = err
+
+    def poll(self):
+        self.left -= 1
+        return self.left <= 0
+
+
+class MockExecutor:
+    def __init__(self, latency_polls=3, fail_on_launch=None, word_bytes=8):
+        self.polls = latency_polls
+        self.fail_on_launch = fail_on_launch      # launch index that reports an error
+        self.launch_count = 0
+        self.batch_sizes = []
+        self.mixed_positions = 0
+
+    def footprint(self, r):
+        return 2 * r.H * ((r.W + 63) // 64) * 8
+
+    def begin(self, r):
+        r.state = {"img": oracle.unpack(np.asarray(r.words), r.W), "nxt": None}
+
+    def launch(self, reqs):
+        self.launch_count += 1
+        self.batch_sizes.append(len(reqs))
+        if len({r.pos for r in reqs}) > 1:
+            self.mixed_positions += 1
+        err = "injected failure" if self.launch_count == self.fail_on_launch else None
+        if err is None:
+            for r in reqs:
+                op, se = r.chain[r.pos]
+                r.state["nxt"] = oracle.sat_apply(op, r.state["img"], se)
+        return Token(self.polls, err)
+
+    def done(self, t):
+        return t.poll()
+
+    def error(self, t):
+        return t.err
+
+    def advance(self, r):
+        r.state["img"], r.state["nxt"] = r.state["nxt"], None
+
+    def begin_download(self, r):
+        r.state["dl"] = Token(2)
+
+    def downloaded(self, r):
+        return r.state["dl"].poll()
+
+    def finish(self, r):
+        return oracle.pack(r.state["img"])
+
+    def release(self, r):
+        r.state = {}
+
+
+def make_requests(n, seed=0, sizes=((130, 40), (300, 77), (64, 9))):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W, H = sizes[i % len(sizes)]
+        img = (rng.random((H, W)) < 0.3).astype(np.uint8)
+        out.append(Request(i, W, H, oracle.pack(img), chain_ses(SERVE_CHAIN)))
+    return out
+
+
+def expected(r):
+    img = oracle.unpack(r.words, r.W)
+    for op, se in r.chain:
+        img = oracle.sat_apply(op, img, se)
+    return oracle.pack(img)
+
+
+def run(server, reqs, every=1):
+    """Submits one request per `every` steps, then drains."""
+    k = 0
+    steps = 0
+    while k < len(reqs) or not server.idle():
+        if k < len(reqs) and steps % every == 0:
+            server.submit(reqs[k])
+            k += 1
+        server.step()
+        steps += 1
+        assert steps < 100000
+
+
+def test_all_requests_complete_with_oracle_results():
+    ex = MockExecutor()
+    s = Server(ex, budget_bytes=1 << 30)
+    reqs = make_requests(12)
+    run(s, reqs, every=2)
+    assert len(s.completed) == 12 and not s.failed
+    for r in reqs:
+        np.testing.assert_array_equal(r.result, expected(r))
+    # continuous batching: later arrivals shared launches with earlier ones
+    assert ex.mixed_positions > 0
+    assert max(ex.batch_sizes) > 1
+
+
+def test_budget_is_never_exceeded_and_admission_is_fifo():
+    reqs = make_requests(10)
+    fp = max(MockExecutor().footprint(r) for r in reqs)
+    ex = MockExecutor()
+    s = Server(ex, budget_bytes=2 * fp)
+    run(s, reqs, every=1)
+    assert s.peak_used <= 2 * fp
+    admits = [r.t_admit for r in sorted(reqs, key=lambda r: r.rid)]
+    assert admits == sorted(admits)
+    assert len(s.completed) == 10
+
+
+def test_request_larger_than_budget_is_rejected():
+    reqs = make_requests(3)
+    big = Request(99, 4096, 4096, np.zeros((4096, 64), np.uint64), chain_ses(SERVE_CHAIN))
+    s = Server(MockExecutor(), budget_bytes=1 << 20)
+    s.submit(big)
+    run(s, reqs)
+    assert big.error and big in s.failed
+    assert len(s.completed) == 3
+
+
+def test_injected_failure_fails_only_its_batch_and_frees_budget():
+    reqs = make_requests(9)
+    ex = MockExecutor(fail_on_launch=2)
+    s = Server(ex, budget_bytes=1 << 30)
+    run(s, reqs, every=1)
+    assert s.failed and all(r.error == "injected failure" for r in s.failed)
+    assert len(s.failed) + len(s.completed) == 9
+    assert s.used == 0
+    for r in s.completed:
+        np.testing.assert_array_equal(r.result, expected(r))
+
+
+def test_chain_is_the_serving_workload():
+    assert [op for op, _ in SERVE_CHAIN] == ["close", "open", "dilate", "erode"]
+    assert chain_ses(SERVE_CHAIN)[0] == ("close", (41, 1, 20, 0))
+    assert chain_ses(SERVE_CHAIN)[2] == ("dilate", (5, 15, 2, 7))
