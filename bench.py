@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--latency-reps", type=int, default=30)
     ap.add_argument("--only", choices=["all", "packed", "rle"], default="all",
                     help="restrict the step (for profiling); the JSON value needs 'all'")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed batch, serving and representation measurements")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     return ap.parse_args()
 
 
@@ -85,6 +88,133 @@ def cpu_baseline(pool, min_seconds):
             "sample": "%d letter page(s) 2550x3300 through the full workload (20 ops brute force on "
                       "bytes + 20 ops as encode(brute(decode(runs))) + conversions), %.1f s"
                       % (pages, dt)}
+
+
+def time_ms(fn, reps=5):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def bench_batched(M, dev, tuner, n=256):
+    """Mixed batch: n pages sized 1275x1650, 2480x3508, 2550x3300 or 5100x6600,
+    each with its own random element (w, h in [1, 63], centred) and operation:
+    per-page launches vs one persistent launch (graph replay), library default
+    tiles and autotuned tiles."""
+    import pagegen
+    items = pagegen.mixed_batch(n, seed=3000, pool_per_size=4)
+    cache = {}
+    srcs, dsts = [], []
+    for it in items:
+        key = id(it.page)
+        if key not in cache:
+            cache[key] = it.page.words()
+        srcs.append(M.Bitmap.from_words(cache[key], it.page.W, device=dev))
+        dsts.append(M.Bitmap.empty(it.page.W, it.page.H, device=dev))
+    px = sum(it.page.W * it.page.H for it in items)
+    alg = sum(2 * 8 * ((it.page.W + 63) // 64) * it.page.H for it in items)
+
+    def per_page():
+        for it, s_, d_ in zip(items, srcs, dsts):
+            M.PACKED[it.op](d_, s_, it.se)
+    t_pp = time_ms(per_page, 3)
+    plan = M.BatchPlan([(d_, s_, it.op, it.se) for it, s_, d_ in zip(items, srcs, dsts)])
+    t_b = time_ms(lambda: plan.run(use_graph=True))
+    widths = {}
+    for it in items:
+        widths.setdefault(it.page.W, (it.page.H, cache[id(it.page)]))
+    t0 = time.perf_counter()
+    tuner.tune_shapes(widths, ops=("erode", "open"), h_values=(5, 16, 40, 63), batch=16)
+    tune_s = time.perf_counter() - t0
+    tuned = []
+    for it, s_, d_ in zip(items, srcs, dsts):
+        tr, sw = tuner.params(it.page.W, it.page.H, it.op, it.se)
+        tuned.append((d_, s_, it.op, it.se, tr, sw))
+    plan_t = M.BatchPlan(tuned)
+    t_t = time_ms(lambda: plan_t.run(use_graph=True))
+    ex = lambda ms: {"ms": ms, "gpixel_s": px / (ms / 1e3) / 1e9, "hbm_gbs": alg / (ms / 1e3) / 1e9,
+                     "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    return {"pages": n, "gpixel": px / 1e9, "alg_bytes": alg, "per_page_launches": ex(t_pp),
+            "persistent_graph": ex(t_b), "persistent_graph_tuned": ex(t_t), "tiles": plan.tiles,
+            "tiles_tuned": plan_t.tiles, "tune_seconds": tune_s}
+
+
+def bench_serving(M, dev, seconds):
+    """Serving: Poisson arrivals of pages sized as in the mixed batch, each with
+    the chain close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5, under a 64 GB
+    HBM budget; served (continuous batching) vs plain per-page path on the
+    same trace.  Saturation rates come from bursts of requests at time 0."""
+    import torch
+    import pagegen
+    from paper_0712_0121_amd import serve
+    pool = []
+    for (W, H) in pagegen.PAGE_SIZES:
+        for k in range(4):
+            p = pagegen.text_page(5000 + 10 * len(pool) + k, W, H)
+            pool.append((W, H, torch.from_numpy(p.words().view(np.int64)).pin_memory()))
+    chain = serve.chain_ses(serve.SERVE_CHAIN)
+    rng = np.random.default_rng(5000)
+
+    def reqs(n):
+        out = []
+        for i in range(n):
+            W, H, w = pool[int(rng.integers(len(pool)))]
+            out.append(serve.Request(i, W, H, w, chain))
+        return out
+
+    budget = 64 << 30
+    runner = serve.PlainRunner(dev)
+    # warm both paths (first launches, allocator pools), then measure
+    # saturation with bursts of requests all arriving at time 0
+    serve.run_trace_plain(runner, reqs(64), np.zeros(64), keep_results=False)
+    serve.run_trace_served(serve.Server(serve.GpuExecutor(dev), budget, keep_results=False), reqs(128),
+                           np.zeros(128))
+    burst = reqs(512)
+    t = time.perf_counter()
+    serve.run_trace_plain(runner, burst, np.zeros(len(burst)), keep_results=False)
+    p0 = len(burst) / (time.perf_counter() - t)
+    burst = reqs(1024)
+    srv = serve.Server(serve.GpuExecutor(dev), budget, keep_results=False)
+    t = time.perf_counter()
+    serve.run_trace_served(srv, burst, np.zeros(len(burst)))
+    p1 = len(burst) / (time.perf_counter() - t)
+    points = []
+    for name, qps in (("0.5x plain saturation", 0.5 * p0), ("0.9x plain saturation", 0.9 * p0),
+                      ("0.9x served saturation", 0.9 * p1)):
+        arrivals = pagegen.poisson_trace(qps, seconds, seed=5001)
+        served = reqs(len(arrivals))
+        srv = serve.Server(serve.GpuExecutor(dev), budget, keep_results=False)
+        serve.run_trace_served(srv, served, arrivals, timeout=seconds * 20 + 60)
+        plain = reqs(len(arrivals))
+        serve.run_trace_plain(runner, plain, arrivals, keep_results=False)
+        points.append({"load": name, "qps": qps, "requests": len(arrivals),
+                       "served": serve.latency_stats(srv.completed, 0.0),
+                       "plain": serve.latency_stats(plain, 0.0),
+                       "served_launches": srv.launches, "served_peak_hbm_gb": srv.peak_used / 2**30})
+    return {"chain": "close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5", "budget_gb": 64,
+            "seconds_per_trace": seconds, "saturation_pages_s": {"plain": p0, "served": p1},
+            "load_points": points}
+
+
+def bench_repr(M, dev, tuner):
+    """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
+    (conversions included), as the autotuner records it."""
+    import pagegen
+    pages = {}
+    for d in (0.01, 0.10, 0.40):
+        p = pagegen.density_page(d, 4000)
+        pages[d] = (p.W, p.H, p.words())
+    tab = tuner.tune_repr(pages)
+    return {k: v for k, v in sorted(tab.items())}
 
 
 def main():
@@ -253,6 +383,18 @@ def main():
                                   "packed_and_rle_40_ops": {"p50": percentile(lat_all, 50),
                                                             "p99": percentile(lat_all, 99)},
                                   "reps": args.latency_reps}
+    if args.only == "all" and not args.no_extras:
+        del rle_src, rle_dst, ws_rle
+        torch.cuda.empty_cache()
+        from paper_0712_0121_amd.tune import Tuner
+        tuner = Tuner(device="cuda:0")
+        out["batched"] = bench_batched(M, dev, tuner)
+        out["repr_choice"] = bench_repr(M, dev, tuner)
+        out["serving"] = bench_serving(M, dev, args.serve_seconds)
+        try:
+            tuner.save()
+        except OSError:
+            pass
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pool, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -7,13 +7,15 @@ e.g. close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5.  The server
 * admits requests first come first served while the device bytes they need
   (two resident page buffers each) fit in an HBM budget; a request larger
   than the whole budget is rejected, others wait;
-* uploads admitted pages on a copy stream, so uploads overlap the kernels;
+* uploads admitted pages on one copy stream and downloads results on
+  another, so uploads, downloads (the two PCIe directions) and kernels
+  overlap;
 * every scheduling step runs the next operation of every admitted request
   that is not already on the device as ONE persistent batched launch
   (morph_batch_launch), so requests at different points of their chains,
   and requests that arrived while others were running, share launches;
   the page stays resident between its operations (two buffers, swapped);
-* downloads finished pages on the copy stream and frees their budget.
+* downloads finished pages and frees their budget.
 
 The scheduler only talks to an executor object, so its logic can be tested
 without a GPU.  GpuExecutor is the product executor; PlainRunner is the
@@ -49,8 +51,7 @@ class Request:
     words: object                  # host (rows, stride) words: numpy uint64 or pinned torch int64
     chain: list                    # [(op, (w, h, cx, cy)), ...]
     arrival: float = 0.0           # seconds on the server clock
-    pos: int = 0                   # operations done
-    busy: bool = False             # an operation is on the device
+    pos: int = 0                   # operations queued
     t_admit: float = -1.0
     t_done: float = -1.0
     result: object = None
@@ -66,9 +67,10 @@ class Server:
     """Admission under a byte budget plus continuous batching (see module
     docstring).  Call submit() as requests arrive and step() in a loop."""
 
-    def __init__(self, executor, budget_bytes: int, max_inflight_batches: int = 2,
-                 clock=time.perf_counter):
+    def __init__(self, executor, budget_bytes: int, max_inflight_batches: int = 4,
+                 clock=time.perf_counter, keep_results: bool = True):
         self.ex = executor
+        self.keep_results = keep_results
         self.budget = int(budget_bytes)
         self.max_batches = max_inflight_batches
         self.clock = clock
@@ -97,46 +99,44 @@ class Server:
 
     def _fail(self, reqs, msg):
         for r in reqs:
+            if r.error is not None or r in self.completed:
+                continue
             r.error = msg
             r.t_done = self.now()
-            r.busy = False
             if r in self.active:
                 self.active.remove(r)
+            if r in self.downloading:
+                self.downloading.remove(r)
             self.used -= self.ex.footprint(r)
             self.ex.release(r)
             self.failed.append(r)
 
     def step(self) -> bool:
-        """One scheduling step; returns True if anything happened."""
+        """One scheduling step; returns True if anything happened.
+
+        Operations of one request are queued in order on one device stream,
+        so the next operation of a request is queued as soon as the previous
+        one has been queued, without waiting for it; a request's download is
+        queued behind its last operation.  At most max_batches launches are
+        outstanding at a time."""
         moved = False
-        # finished launches: advance their requests
         while self.batches and self.ex.done(self.batches[0][0]):
             token, reqs = self.batches.popleft()
             err = self.ex.error(token)
             if err:
                 self._fail(reqs, err)
-                moved = True
-                continue
-            for r in reqs:
-                self.ex.advance(r)
-                r.pos += 1
-                r.busy = False
-                if r.pos == len(r.chain):
-                    self.active.remove(r)
-                    self.ex.begin_download(r)
-                    self.downloading.append(r)
             moved = True
-        # finished downloads
         still = []
         for r in self.downloading:
-            if self.ex.downloaded(r):
-                r.result = self.ex.finish(r)
+            if r.error is None and self.ex.downloaded(r):
+                res = self.ex.finish(r)
+                r.result = res if self.keep_results else None
                 r.t_done = self.now()
                 self.ex.release(r)
                 self.used -= self.ex.footprint(r)
                 self.completed.append(r)
                 moved = True
-            else:
+            elif r.error is None:
                 still.append(r)
         self.downloading = still
         # admission, first come first served
@@ -148,20 +148,24 @@ class Server:
             self.ex.begin(r)
             self.active.append(r)
             moved = True
-        # next operation of every idle admitted request, as one launch
-        if len(self.batches) < self.max_batches:
-            ready = [r for r in self.active if not r.busy and r.pos < len(r.chain)]
-            if ready:
-                try:
-                    token = self.ex.launch(ready)
-                except Exception as e:          # the launch could not be queued
-                    self._fail(ready, "launch failed: %s" % e)
-                    return True
-                for r in ready:
-                    r.busy = True
-                self.batches.append((token, ready))
-                self.launches += 1
-                moved = True
+        # the next operation of every admitted request, as one launch
+        if self.active and len(self.batches) < self.max_batches:
+            ready = list(self.active)
+            try:
+                token = self.ex.launch(ready)
+            except Exception as e:          # the launch could not be queued
+                self._fail(ready, "launch failed: %s" % e)
+                return True
+            self.batches.append((token, ready))
+            self.launches += 1
+            for r in ready:
+                self.ex.advance(r)
+                r.pos += 1
+                if r.pos == len(r.chain):
+                    self.active.remove(r)
+                    self.ex.begin_download(r)
+                    self.downloading.append(r)
+            moved = True
         return moved
 
     def idle(self) -> bool:
@@ -185,7 +189,8 @@ class GpuExecutor:
         self.M, self.torch = M, torch
         self.device = torch.device(device)
         self.compute = torch.cuda.Stream(device=self.device)
-        self.copy = torch.cuda.Stream(device=self.device)
+        self.copy = torch.cuda.Stream(device=self.device)        # uploads
+        self.down = torch.cuda.Stream(device=self.device)        # downloads (the other PCIe direction)
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         self.staging = [torch.empty(ws_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(staging_slots)]
         self.staging_ev = [None] * staging_slots
@@ -201,9 +206,10 @@ class GpuExecutor:
             host = torch.from_numpy(np.ascontiguousarray(host).view(np.int64))
         a = M.Bitmap.empty(r.W, r.H, device=self.device)
         b = M.Bitmap.empty(r.W, r.H, device=self.device)
-        for t in (a.words, b.words):           # used on both side streams
+        for t in (a.words, b.words):           # used on the side streams
             t.record_stream(self.copy)
             t.record_stream(self.compute)
+            t.record_stream(self.down)
         with torch.cuda.stream(self.copy):
             a.words.copy_(host[:, : a.stride], non_blocking=True)
             ev = torch.cuda.Event()
@@ -246,11 +252,11 @@ class GpuExecutor:
         torch = self.torch
         st = r.state
         out = torch.empty((r.H, st["cur"].stride), dtype=torch.int64, pin_memory=True)
-        with torch.cuda.stream(self.copy):
-            self.copy.wait_event(st["ev"])
+        with torch.cuda.stream(self.down):
+            self.down.wait_event(st["ev"])
             out.copy_(st["cur"].words, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.copy)
+            ev.record(self.down)
         st["out"], st["down"] = out, ev
 
     def downloaded(self, r: Request) -> bool:
@@ -321,7 +327,7 @@ def run_trace_served(server: Server, requests, arrivals, timeout=120.0):
     return server.completed
 
 
-def run_trace_plain(runner: PlainRunner, requests, arrivals, clock=time.perf_counter):
+def run_trace_plain(runner: PlainRunner, requests, arrivals, clock=time.perf_counter, keep_results=True):
     """Serves the same trace with the plain path: requests in arrival order,
     each started when it has arrived and the previous one is done."""
     t0 = clock()
@@ -331,7 +337,8 @@ def run_trace_plain(runner: PlainRunner, requests, arrivals, clock=time.perf_cou
         r.arrival = float(arrivals[k])
         while clock() - t0 < r.arrival:
             time.sleep(10e-6)
-        r.result = runner.run_one(r)
+        res = runner.run_one(r)
+        r.result = res if keep_results else None
         r.t_done = clock() - t0
     return [requests[k] for k in order]
 

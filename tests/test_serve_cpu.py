@@ -39,11 +39,12 @@ class MockExecutor:
         if len({r.pos for r in reqs}) > 1:
             self.mixed_positions += 1
         err = "injected failure" if self.launch_count == self.fail_on_launch else None
-        if err is None:
-            for r in reqs:
-                op, se = r.chain[r.pos]
-                r.state["nxt"] = oracle.sat_apply(op, r.state["img"], se)
-        return Token(self.polls, err)
+        tok = Token(self.polls, err)
+        for r in reqs:
+            op, se = r.chain[r.pos]
+            r.state["nxt"] = oracle.sat_apply(op, r.state["img"], se)
+            r.state["last"] = tok
+        return tok
 
     def done(self, t):
         return t.poll()
@@ -58,7 +59,8 @@ class MockExecutor:
         r.state["dl"] = Token(2)
 
     def downloaded(self, r):
-        return r.state["dl"].poll()
+        # a download finishes only after the request's last launch
+        return r.state["dl"].poll() and r.state["last"].left <= 0
 
     def finish(self, r):
         return oracle.pack(r.state["img"])
