@@ -234,6 +234,44 @@ int64_t morph_batch_workspace_bytes(const morph_page_desc_t *descs, int32_t n);
 int morph_batch_launch(const morph_page_desc_t *descs, int32_t n, void *ws, size_t ws_bytes,
                        void *host_staging, size_t staging_bytes, morph_stream_t stream);
 
+/* ---- tracing (benchmarks and profiling) --------------------------------- */
+/*
+ * While tracing is on, the library records a pair of HIP events around every
+ * launch of the kernels below, on the stream of the call, and the run-length
+ * kernels add the runs they read and write to counters in the device buffer
+ * given to morph_trace_begin.  morph_trace_end waits for the stream and
+ * returns, per kernel, the number of launches, the summed event-measured
+ * duration and the algorithmic bytes: what the operation has to move, i.e.
+ * one read of its input and one write of its output (packed: 8 bytes per
+ * word; runs: 8 bytes per run plus 4 per row count), not what the kernel
+ * happens to re-read.  Tracing state is process-wide: trace one thread at a
+ * time.
+ */
+enum {
+    MORPH_K_RECT = 0,          /* fused packed rectangle kernel (per-op launches) */
+    MORPH_K_RECT_BATCH = 1,    /* persistent batched packed kernel */
+    MORPH_K_PACK_TO_RLE = 2,   /* bitmap -> runs (count and emit launches) */
+    MORPH_K_RLE_TO_PACK = 3,   /* runs -> bitmap */
+    MORPH_K_ROW_ERODE = 4,     /* within-line pass on runs */
+    MORPH_K_COL_AND = 5,       /* between-line doubling step on runs */
+    MORPH_K_PACK_ROWS = 6,     /* final packing of run rows into CSR */
+    MORPH_K_COUNT = 7
+};
+typedef struct {
+    int64_t launches;
+    double ms;                  /* sum of event-measured launch durations */
+    double bytes;               /* algorithmic bytes over all launches */
+} morph_kernel_trace_t;
+/* Device memory the counters need (128-byte aligned). */
+#define MORPH_TRACE_BYTES (MORPH_K_COUNT * 2 * 256 * 128)
+/* dev_counters: at least MORPH_TRACE_BYTES of device memory, used until
+ * morph_trace_end. */
+int morph_trace_begin(void *dev_counters, size_t bytes, morph_stream_t stream);
+/* out: MORPH_K_COUNT entries. */
+int morph_trace_end(morph_kernel_trace_t *out, morph_stream_t stream);
+/* Name of a kernel id. */
+const char *morph_kernel_name(int kernel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ __all__ = [
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
     "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes",
-    "morph_batch_launch",
+    "morph_batch_launch", "Trace",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack",
 ]
 
@@ -63,6 +63,13 @@ class morph_rle_t(ctypes.Structure):
 
 class morph_se_t(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32)]
+
+
+class morph_kernel_trace_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+MORPH_K_COUNT = 7
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -94,6 +101,9 @@ def _load():
         "morph_batch_plan_destroy": (None, [P]),
         "morph_batch_workspace_bytes": (I64, [ctypes.POINTER(morph_page_desc_t), I32]),
         "morph_batch_launch": (ctypes.c_int, [ctypes.POINTER(morph_page_desc_t), I32, P, SZ, P, SZ, P]),
+        "morph_trace_begin": (ctypes.c_int, [P, SZ, P]),
+        "morph_trace_end": (ctypes.c_int, [ctypes.POINTER(morph_kernel_trace_t), P]),
+        "morph_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -390,6 +400,32 @@ def morph_batch_launch(items, ws, staging=None, stream=None):
     else:
         sp, sn = None, 0
     _check(_lib.morph_batch_launch(arr, n, p, nb, sp, sn, _stream(stream)), "morph_batch_launch")
+
+
+class Trace:
+    """Context manager around morph_trace_begin / morph_trace_end: collects,
+    per library kernel, launches, event-measured milliseconds and
+    algorithmic bytes of everything queued on `stream` inside it."""
+
+    def __init__(self, stream=None):
+        self.stream = stream
+        self.result = {}
+
+    def __enter__(self):
+        nbytes = MORPH_K_COUNT * 2 * 256 * 128
+        self.buf = torch.empty(nbytes // 8 + 16, dtype=torch.int64, device="cuda")
+        base = (self.buf.data_ptr() + 127) // 128 * 128
+        _check(_lib.morph_trace_begin(ctypes.c_void_p(base), nbytes, _stream(self.stream)),
+               "morph_trace_begin")
+        return self
+
+    def __exit__(self, *exc):
+        arr = (morph_kernel_trace_t * MORPH_K_COUNT)()
+        _check(_lib.morph_trace_end(arr, _stream(self.stream)), "morph_trace_end")
+        self.result = {_lib.morph_kernel_name(k).decode(): {"launches": int(arr[k].launches), "ms": float(arr[k].ms),
+                                                             "bytes": float(arr[k].bytes)}
+                       for k in range(MORPH_K_COUNT) if arr[k].launches}
+        return False
 
 
 # ------------------------------------------------------------- conveniences

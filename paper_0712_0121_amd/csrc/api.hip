@@ -14,6 +14,9 @@ namespace morph {
 
 static thread_local char g_hip_err[256] = "";
 
+bool trace_pause();                 // tracing off; returns the previous state
+void trace_resume(bool prev);        // (both defined with the tracing code)
+
 void set_hip_error(hipError_t e)
 {
     std::snprintf(g_hip_err, sizeof g_hip_err, "%s (%d)", hipGetErrorString(e), (int)e);
@@ -185,6 +188,7 @@ struct morph_batch_plan {
     int *queue_dev = nullptr;
     int ntiles = 0;
     int nblocks = 0;
+    double alg_bytes = 0;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -306,6 +310,13 @@ static int build_batch(const morph_page_desc_t *descs, int32_t n, std::vector<Re
     return MORPH_OK;
 }
 
+static double batch_alg_bytes(const std::vector<RectPage> &pages)
+{
+    double b = 0;
+    for (const RectPage &p : pages) b += 16.0 * p.nw * (double)p.H;
+    return b;
+}
+
 // Device layout of an uploaded batch: queue counter, page table, tile list.
 static size_t batch_bytes(size_t npages, size_t ntiles)
 {
@@ -345,6 +356,7 @@ int morph_batch_plan_create(morph_batch_plan_t **plan, const morph_page_desc_t *
     }
     pl->ntiles = (int)tiles.size();
     pl->nblocks = std::max(1, std::min(pl->ntiles, 2 * device_cu_count()));
+    for (const RectPage &p : pages) pl->alg_bytes += 16.0 * p.nw * (double)p.H;
     *plan = pl;
     return MORPH_OK;
 }
@@ -387,8 +399,8 @@ int morph_batch_launch(const morph_page_desc_t *descs, int32_t n, void *ws, size
         (!host_staging && (e = hipStreamSynchronize(s)) != hipSuccess) ||
         (e = launch_reset_counter((int *)d, s)) != hipSuccess ||
         (e = launch_rect_batch((const RectPage *)(d + po), (const TileRef *)(d + to), (int)tiles.size(),
-                               (int *)d, std::max(1, std::min((int)tiles.size(), 2 * device_cu_count())), s)) !=
-            hipSuccess) {
+                               (int *)d, std::max(1, std::min((int)tiles.size(), 2 * device_cu_count())), s,
+                               batch_alg_bytes(pages))) != hipSuccess) {
         set_hip_error(e);
         return MORPH_E_HIP;
     }
@@ -406,7 +418,7 @@ int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t 
     if (!use_graph) {
         if ((e = launch_reset_counter(plan->queue_dev, s)) != hipSuccess ||
             (e = launch_rect_batch(plan->pages_dev, plan->tiles_dev, plan->ntiles, plan->queue_dev,
-                                   plan->nblocks, s)) != hipSuccess) {
+                                   plan->nblocks, s, plan->alg_bytes)) != hipSuccess) {
             set_hip_error(e);
             return MORPH_E_HIP;
         }
@@ -420,8 +432,10 @@ int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t 
             return MORPH_E_HIP;
         }
         hipError_t e1 = launch_reset_counter(plan->queue_dev, cs);
-        hipError_t e2 = launch_rect_batch(plan->pages_dev, plan->tiles_dev, plan->ntiles,
-                                          plan->queue_dev, plan->nblocks, cs);
+        const bool was_on = trace_pause();      // no event records inside the graph
+        hipError_t e2 = launch_rect_batch(plan->pages_dev, plan->tiles_dev, plan->ntiles, plan->queue_dev,
+                                          plan->nblocks, cs, plan->alg_bytes);
+        trace_resume(was_on);
         e = hipStreamEndCapture(cs, &plan->graph);
         if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
             set_hip_error(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e));
@@ -434,10 +448,12 @@ int morph_batch_run(morph_batch_plan_t *plan, int32_t use_graph, morph_stream_t 
             return MORPH_E_HIP;
         }
     }
+    trace_before(MORPH_K_RECT_BATCH, s);
     if ((e = hipGraphLaunch(plan->exec, s)) != hipSuccess) {
         set_hip_error(e);
         return MORPH_E_HIP;
     }
+    trace_after(MORPH_K_RECT_BATCH, s, plan->alg_bytes);
     return MORPH_OK;
 }
 
@@ -574,6 +590,131 @@ int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
     const int rc = rle_validate(*r, (hipStream_t)stream, &e);
     if (rc == MORPH_E_HIP) set_hip_error(e);
     return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tracing
+namespace morph {
+
+namespace {
+struct TraceRec {
+    hipEvent_t a, b;
+    int kernel;
+    double bytes;
+};
+struct Trace {
+    bool on = false;
+    unsigned long long *dev = nullptr;
+    std::vector<TraceRec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t pending = nullptr;
+} g_trace;
+
+hipEvent_t trace_event()
+{
+    hipEvent_t e = nullptr;
+    if (!g_trace.pool.empty()) {
+        e = g_trace.pool.back();
+        g_trace.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+__global__ void zero_kernel(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+bool trace_on() { return g_trace.on; }
+
+bool trace_pause()
+{
+    const bool prev = g_trace.on;
+    g_trace.on = false;
+    return prev;
+}
+
+void trace_resume(bool prev) { g_trace.on = prev; }
+
+unsigned long long *trace_counters() { return g_trace.on ? g_trace.dev : nullptr; }
+
+void trace_before(int kernel, hipStream_t s)
+{
+    (void)kernel;
+    if (!g_trace.on) return;
+    g_trace.pending = trace_event();
+    if (g_trace.pending) hipEventRecord(g_trace.pending, s);
+}
+
+void trace_after(int kernel, hipStream_t s, double alg_bytes)
+{
+    if (!g_trace.on || !g_trace.pending) return;
+    hipEvent_t b = trace_event();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_trace.recs.push_back(TraceRec{g_trace.pending, b, kernel, alg_bytes});
+    g_trace.pending = nullptr;
+}
+
+}  // namespace morph
+
+extern "C" {
+
+const char *morph_kernel_name(int k)
+{
+    static const char *names[MORPH_K_COUNT] = {"rect_kernel", "rect_batch_kernel", "pack_to_rle_kernel",
+                                               "rle_to_pack_kernel", "row_erode_kernel", "col_and_kernel",
+                                               "pack_rows_kernel"};
+    return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
+}
+
+int morph_trace_begin(void *dev_counters, size_t bytes, morph_stream_t stream)
+{
+    if (!dev_counters || bytes < MORPH_TRACE_BYTES || (((uintptr_t)dev_counters) & 127)) return MORPH_E_INVAL;
+    g_trace.on = true;
+    g_trace.dev = (unsigned long long *)dev_counters;
+    g_trace.recs.clear();
+    const int n = MORPH_TRACE_BYTES / 8;
+    hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, g_trace.dev, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_trace_end(morph_kernel_trace_t *out, morph_stream_t stream)
+{
+    if (!out) return MORPH_E_INVAL;
+    for (int k = 0; k < MORPH_K_COUNT; k++) out[k] = morph_kernel_trace_t{0, 0.0, 0.0};
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    std::vector<unsigned long long> raw(MORPH_TRACE_BYTES / 8, 0);
+    if (e == hipSuccess && g_trace.dev)
+        e = hipMemcpy(raw.data(), g_trace.dev, MORPH_TRACE_BYTES, hipMemcpyDeviceToHost);
+    // per kernel: 2 counters (read, written) x 256 slots, one slot every 16 words
+    unsigned long long runs[2 * MORPH_K_COUNT] = {0};
+    for (int c = 0; c < 2 * MORPH_K_COUNT; c++)
+        for (int sl = 0; sl < 256; sl++) runs[c] += raw[((size_t)c * 256 + sl) * 16];
+    for (const TraceRec &r : g_trace.recs) {
+        float ms = 0.f;
+        if (e == hipSuccess) hipEventElapsedTime(&ms, r.a, r.b);
+        out[r.kernel].launches++;
+        out[r.kernel].ms += ms;
+        out[r.kernel].bytes += r.bytes;
+        g_trace.pool.push_back(r.a);
+        g_trace.pool.push_back(r.b);
+    }
+    // run-length kernels: 8 bytes per run read and written on top of the
+    // row counts the host added
+    for (int k = 0; k < MORPH_K_COUNT; k++) out[k].bytes += 8.0 * (double)(runs[2 * k] + runs[2 * k + 1]);
+    g_trace.recs.clear();
+    g_trace.on = false;
+    g_trace.dev = nullptr;
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
 }
 
 }  // extern "C"

@@ -53,7 +53,7 @@ struct TileRef {
     int page, band, strip, pad;
 };
 hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev, int ntiles,
-                             int *queue_dev, int nblocks, hipStream_t stream);
+                             int *queue_dev, int nblocks, hipStream_t stream, double alg_bytes);
 hipError_t launch_reset_counter(int *queue_dev, hipStream_t stream);
 int device_cu_count();
 
@@ -68,5 +68,12 @@ size_t scan_workspace(int64_t n);
 int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
 
 void set_hip_error(hipError_t e);
+
+// Tracing: events around launches while on; run counters for the
+// run-length kernels (device address, or nullptr when tracing is off).
+bool trace_on();
+void trace_before(int kernel, hipStream_t s);
+void trace_after(int kernel, hipStream_t s, double alg_bytes);
+unsigned long long *trace_counters();   // [kernel*2] runs read, [kernel*2+1] runs written
 
 }  // namespace morph

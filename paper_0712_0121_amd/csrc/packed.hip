@@ -631,15 +631,19 @@ hipError_t launch_rect(const RectPage &p, int npages, hipStream_t stream)
     if (T <= 0) return hipSuccess;
     if (!tile_fits(p) || T > 0x7fffffffLL) return hipErrorInvalidValue;
     const int grid = (int)std::min<long long>(T, 2LL * device_cu_count());
+    trace_before(MORPH_K_RECT, stream);
     hipLaunchKernelGGL(rect_kernel, dim3(grid), dim3(kThreads), 0, stream, p, (int)T);
+    trace_after(MORPH_K_RECT, stream, 16.0 * p.nw * (double)p.H * npages);
     return hipGetLastError();
 }
 
 hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev, int ntiles,
-                             int *queue_dev, int nblocks, hipStream_t stream)
+                             int *queue_dev, int nblocks, hipStream_t stream, double alg_bytes)
 {
+    trace_before(MORPH_K_RECT_BATCH, stream);
     hipLaunchKernelGGL(rect_batch_kernel, dim3(nblocks), dim3(kThreads), 0, stream, pages_dev,
                        tiles_dev, ntiles, queue_dev);
+    trace_after(MORPH_K_RECT_BATCH, stream, alg_bytes);
     return hipGetLastError();
 }
 

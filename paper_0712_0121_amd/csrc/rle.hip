@@ -35,6 +35,18 @@ constexpr int kRowWaves = 4;                             // rows per workgroup (
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Trace counters: runs read / written, spread over 256 slots (one 128-byte
+// line each) so that concurrent groups rarely add to the same address.
+constexpr int kTraceSlots = 256, kTraceStride = 16;
+
+__device__ __forceinline__ void trace_add(unsigned long long *tr, unsigned long long in, unsigned long long out)
+{
+    const int slot = (int)((blockIdx.x * 16u + (threadIdx.x >> 4)) & (kTraceSlots - 1));
+    if (in) atomicAdd(tr + (long long)slot * kTraceStride, in);
+    if (out) atomicAdd(tr + (long long)(kTraceSlots + slot) * kTraceStride, out);
+}
+
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_incl_scan(int x)
 {
@@ -135,7 +147,7 @@ template <bool EMIT>
 __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
     const uint64_t *__restrict__ words, int nw, int stride, int H, int R, long long page_words,
     uint64_t padmask, int *__restrict__ counts, const int *__restrict__ row_ptr,
-    int *__restrict__ runs, long long cap)
+    int *__restrict__ runs, long long cap, unsigned long long *trace)
 {
     const int r = blockIdx.x * kRowWaves + (int)(threadIdx.x >> 6);
     if (r >= R) return;                    // whole wave
@@ -180,6 +192,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
         prev = (uint64_t)__shfl((int)(a >> 63), 63, 64);
     }
     if (!EMIT && lane == 0) counts[r] = cstart;
+    if (EMIT && trace && lane == 0) trace_add(trace, 0, (unsigned long long)cstart);
 }
 
 // -------------------------------------------------------- runs -> packed
@@ -188,7 +201,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
 __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict__ row_ptr,
                                                           const int *__restrict__ runs, int nw,
                                                           int R, int H, uint64_t *__restrict__ words,
-                                                          int stride, long long page_words)
+                                                          int stride, long long page_words,
+                                                          unsigned long long *trace)
 {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long long)R * nw) return;
@@ -211,6 +225,7 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
         v |= hiMask & ~((1ull << a) - 1);
     }
     words[(long long)page * page_words + (long long)y * stride + j] = v;
+    if (trace && j == 0) trace_add(trace, (unsigned long long)(row_ptr[r + 1] - row_ptr[r]), 0);
 }
 
 // ------------------------------------------------- rows in two layouts
@@ -269,7 +284,8 @@ __device__ __forceinline__ int group_incl_scan(int x)
 // One group of 16 lanes per row, lanes over runs, compaction by ballot.
 __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W, int w, int cx, int comp_in,
                                                         int *__restrict__ out_cnt,
-                                                        int *__restrict__ out_runs, long long cap_row)
+                                                        int *__restrict__ out_runs, long long cap_row,
+                                                        unsigned long long *trace)
 {
     const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= R) return;                    // whole group
@@ -305,20 +321,13 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
         }
         carry += __popc(gm);
     }
-    if (gl == 0) out_cnt[r] = (int)min((long long)carry, cap_row);
+    if (gl == 0) {
+        out_cnt[r] = (int)min((long long)carry, cap_row);
+        if (trace) trace_add(trace, (unsigned long long)n, (unsigned long long)carry);
+    }
 }
 
 // ----------------------------------------------------- between-line pass
-constexpr int kStageInts = 512;             // LDS ints per group for the two rows of a step
-
-// Orders a wave's LDS accesses (all lanes of a group are in one wave).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-}
-
 // Intersection of run lists A (na runs) and B (nb runs) into o, by the
 // lanes of one group: lane k takes runs k, k+16, ... of A, finds the first
 // run of B that ends after it starts, and emits every overlap in order.
@@ -362,13 +371,12 @@ __device__ __forceinline__ int group_intersect(const int *A, int na, const int *
 // is the intersection of rows r and r + K of the input, where input row x is
 // stored row x - off if that lies in [0, real), and otherwise a full row
 // [0, W) (outside the image erosion sees 1s).  NA rows per page come in,
-// NA - K go out.  One group of lanes per output row; both rows are first
-// copied to LDS when they fit, so the searches run there.
+// NA - K go out.  One group of lanes per output row.
 __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, int P,
                                                       int W, int *__restrict__ out_cnt,
-                                                      int *__restrict__ out_runs, long long cap_row)
+                                                      int *__restrict__ out_runs, long long cap_row,
+                                                      unsigned long long *trace)
 {
-    __shared__ int stage[kGroupsPerBlock][kStageInts];
     const int NB = NA - K;
     const long long t = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
     if (t >= (long long)P * NB) return;     // whole group
@@ -382,6 +390,7 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
             o[0] = 0;
             o[1] = W;
             out_cnt[t] = 1;
+            if (trace) trace_add(trace, 0, 1ull);
         }
         return;
     }
@@ -395,7 +404,14 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
             o[2 * k] = src[2 * k];
             o[2 * k + 1] = src[2 * k + 1];
         }
-        if (gl == 0) out_cnt[t] = n;
+        if (gl == 0) {
+            out_cnt[t] = n;
+            // input runs: the A row (if stored); the B row only where it is
+            // never an A row (r + K >= NB)
+            if (trace)
+                trace_add(trace, (unsigned long long)((va ? n : 0) + (vb && r + K >= NB ? n : 0)),
+                          (unsigned long long)n);
+        }
         return;
     }
     long long ba, bb;
@@ -404,17 +420,11 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     row_span(in, (long long)page * real + ib, bb, nb);
     const int *A = in.runs + 2 * ba;
     const int *B = in.runs + 2 * bb;
-    int cnt;
-    if (2 * (na + nb) <= kStageInts) {
-        int *sm = stage[threadIdx.x >> 4];
-        for (int k = gl; k < 2 * na; k += kGroup) sm[k] = A[k];
-        for (int k = gl; k < 2 * nb; k += kGroup) sm[2 * na + k] = B[k];
-        wave_lds_sync();
-        cnt = group_intersect(sm, na, sm + 2 * na, nb, o, cap_row);
-    } else {
-        cnt = group_intersect(A, na, B, nb, o, cap_row);
+    const int cnt = group_intersect(A, na, B, nb, o, cap_row);
+    if (gl == 0) {
+        out_cnt[t] = (int)min((long long)cnt, cap_row);
+        if (trace) trace_add(trace, (unsigned long long)(na + (r + K >= NB ? nb : 0)), (unsigned long long)cnt);
     }
-    if (gl == 0) out_cnt[t] = (int)min((long long)cnt, cap_row);
 }
 
 // ---------------------------------------------------------- final packing
@@ -437,7 +447,8 @@ __global__ __launch_bounds__(256) void gap_count_kernel(RowsIn in, int R, int W,
 // Copies slot rows (or their complements) to CSR rows at row_ptr.
 __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W, int comp,
                                                         const int *__restrict__ row_ptr,
-                                                        int *__restrict__ out_runs, long long cap)
+                                                        int *__restrict__ out_runs, long long cap,
+                                                        unsigned long long *trace)
 {
     const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= R) return;
@@ -449,6 +460,7 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
     const long long o = row_ptr[r];
     const int nout = row_ptr[r + 1] - row_ptr[r];
     const int skip = (comp && n > 0 && rr[0] == 0) ? 1 : 0;
+    if (trace && gl == 0) trace_add(trace, (unsigned long long)n, (unsigned long long)nout);
     for (int k = gl; k < nout; k += kGroup) {
         int s, e;
         if (comp) {
@@ -507,6 +519,12 @@ static hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipSt
 
 static size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// This kernel's block of trace counters (nullptr when tracing is off).
+static unsigned long long *trace_block(unsigned long long *tr, int kernel)
+{
+    return tr ? tr + (long long)kernel * 2 * kTraceSlots * kTraceStride : nullptr;
+}
+
 hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws, hipStream_t s)
 {
     const int R = src.height * src.npages;
@@ -516,13 +534,16 @@ hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, vo
     int *tmp = (int *)((char *)ws + r256((size_t)R * sizeof(int)));
     const long long pw = (long long)src.stride_words * src.height;
     const unsigned g = blocks_for(R, kRowWaves);
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_PACK_TO_RLE, s);
     hipLaunchKernelGGL((pack_to_rle_kernel<false>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
-                       src.stride_words, src.height, R, pw, pad, counts, nullptr, nullptr, 0LL);
+                       src.stride_words, src.height, R, pw, pad, counts, nullptr, nullptr, 0LL, nullptr);
     hipError_t e = exclusive_scan(counts, R, dst.row_ptr, tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((pack_to_rle_kernel<true>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
                        src.stride_words, src.height, R, pw, pad, nullptr, dst.row_ptr, dst.runs,
-                       (long long)dst.capacity);
+                       (long long)dst.capacity, trace_block(tr, MORPH_K_PACK_TO_RLE));
+    trace_after(MORPH_K_PACK_TO_RLE, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
 
@@ -531,9 +552,12 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
     const int R = src.height * src.npages;
     const int nw = (src.width + 63) / 64;
     const long long total = (long long)R * nw;
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_RLE_TO_PACK, s);
     hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, src.row_ptr,
                        src.runs, nw, R, src.height, dst.words, dst.stride_words,
-                       (long long)dst.stride_words * dst.height);
+                       (long long)dst.stride_words * dst.height, trace_block(tr, MORPH_K_RLE_TO_PACK));
+    trace_after(MORPH_K_RLE_TO_PACK, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
 
@@ -587,8 +611,12 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
                        const RleWs &L, int to, hipStream_t s, hipError_t *err)
 {
     const int R = P * H;
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_ROW_ERODE, s);
     hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
-                       cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row);
+                       cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row,
+                       trace_block(tr, MORPH_K_ROW_ERODE));
+    trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
     int cur = to;
     // rows of the extended page: 0 .. H+h-2, row x being image row x - cy
     int off = cy, real = H, NA = H + h - 1;
@@ -599,9 +627,11 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
     for (int k = 0; k < n; k++) {
         const int K = offs[k], NB = NA - K;
         const int nxt = 1 - cur;
+        trace_before(MORPH_K_COL_AND, s);
         hipLaunchKernelGGL(col_and_kernel, dim3(blocks_for((long long)P * NB, kGroupsPerBlock)), dim3(256), 0, s,
                            slot_rows(L, cur), off, real, NA, K, P, W, L.cnt[nxt], L.runs[nxt],
-                           (long long)L.cap_row);
+                           (long long)L.cap_row, trace_block(tr, MORPH_K_COL_AND));
+        trace_after(MORPH_K_COL_AND, s, 4.0 * P * ((double)real + NB));
         cur = nxt;
         off = 0;
         real = NB;
@@ -616,6 +646,8 @@ static hipError_t finish(const RleWs &L, int b, int comp, const morph_rle_t &dst
 {
     const int R = dst.height * dst.npages;
     const int *counts = L.cnt[b];
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_PACK_ROWS, s);
     if (comp) {
         hipLaunchKernelGGL(gap_count_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, s, slot_rows(L, b), R, W,
                            L.fcount);
@@ -624,7 +656,9 @@ static hipError_t finish(const RleWs &L, int b, int comp, const morph_rle_t &dst
     hipError_t e = exclusive_scan(counts, R, dst.row_ptr, L.tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pack_rows_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, slot_rows(L, b), R,
-                       W, comp, dst.row_ptr, dst.runs, (long long)dst.capacity);
+                       W, comp, dst.row_ptr, dst.runs, (long long)dst.capacity,
+                       trace_block(tr, MORPH_K_PACK_ROWS));
+    trace_after(MORPH_K_PACK_ROWS, s, 4.0 * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
 

@@ -171,3 +171,24 @@ def test_rle_empty_and_full():
         img = rnd_img(1, 30, 130, p)
         for op in pagegen.OPS:
             assert_rle_equal(rle_op(op, img, (5, 5, 2, 2)), oracle.apply(op, img, (5, 5, 2, 2)))
+
+
+def test_trace_counts_launches_and_bytes():
+    """Tracing: rect_kernel bytes are one read and one write of the page;
+    pack_to_rle counts exactly the runs it wrote."""
+    img = pagegen.small_page(1001).img
+    W, H = img.shape[1], img.shape[0]
+    src = M.Bitmap.from_words(oracle.pack(img), W)
+    with M.Trace() as tr:
+        M.rect_packed("erode", src, (3, 3, 1, 1))
+        r = M.pack_to_rle(src)
+        M.rect_rle("dilate", r, (5, 5, 2, 2))
+    res = tr.result
+    assert res["rect_kernel"]["launches"] == 1
+    assert res["rect_kernel"]["bytes"] == 16 * 8 * H
+    assert res["rect_kernel"]["ms"] > 0
+    n = int(oracle.rle_encode(img)[0][-1])
+    assert res["pack_to_rle_kernel"]["bytes"] == 8 * 8 * H + 4 * (H + 1) + 8 * n
+    assert res["col_and_kernel"]["launches"] == 3          # offsets 1, 2, then 1
+    assert res["row_erode_kernel"]["launches"] == 1
+    assert res["pack_rows_kernel"]["launches"] == 1
