@@ -35,6 +35,18 @@ constexpr int kRowWaves = 4;                             // rows per workgroup (
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Workgroups are dealt to the 8 XCDs round robin, and each XCD has its own
+// L2.  Kernels whose neighbouring rows share cache lines (a row and the row
+// K below it, or the partial lines where one row's runs end and the next
+// row's begin) take their rows from this logical index instead of
+// blockIdx.x: it gives every XCD one contiguous range of blocks.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned n = gridDim.x, b = blockIdx.x;
+    const unsigned x = b & 7u, q = n >> 3, rem = n & 7u;
+    return x * q + min(x, rem) + (b >> 3);
+}
+
 // Trace counters: runs read / written, spread over 256 slots (one 128-byte
 // line each) so that concurrent groups rarely add to the same address.
 constexpr int kTraceSlots = 256, kTraceStride = 16;
@@ -264,15 +276,22 @@ __device__ __forceinline__ unsigned group_ballot(bool p)
     return (unsigned)(m >> (lane_id() & ~(kGroup - 1))) & 0xffffu;
 }
 
+// Inclusive prefix sum over the 16 lanes of a group.  A DPP row is 16
+// lanes, so row_shr moves values within the group only and lanes below the
+// shift read 0: no LDS traffic.
 __device__ __forceinline__ int group_incl_scan(int x)
 {
-    const int gl = glane();
-#pragma unroll
-    for (int d = 1; d < kGroup; d <<= 1) {
-        const int t = __shfl_up(x, d, kGroup);
-        if (gl >= d) x += t;
-    }
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);    // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);    // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);    // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);    // row_shr:8
     return x;
+}
+
+// Lane 15 of this lane's group (DPP row_newbcast:15).
+__device__ __forceinline__ int group_last(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x15f, 0xf, 0xf, false);
 }
 
 // ------------------------------------------------------ within-line pass
@@ -287,7 +306,7 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
                                                         int *__restrict__ out_runs, long long cap_row,
                                                         unsigned long long *trace)
 {
-    const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    const long long r = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= R) return;                    // whole group
     const int gl = glane();
     long long base;
@@ -361,7 +380,52 @@ __device__ __forceinline__ int group_intersect(const int *A, int na, const int *
                 idx++;
             }
         }
-        carry += __shfl(inc, kGroup - 1, kGroup);
+        carry += group_last(inc);
+    }
+    return carry;
+}
+
+// The same intersection with row A in registers (lane k holds runs k + 16 m
+// of A) and row B staged in this group's LDS window.  Every load of both
+// rows has been issued before the first search step, so a group waits for
+// global memory twice (counts, then runs) instead of once per search step.
+constexpr int kStageRuns = 128;                 // runs of a row a group stages
+constexpr int kARegs = kStageRuns / kGroup;     // runs of row A per lane
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+__device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], int na, const int2 *sB, int nb,
+                                                      int2 *o, long long cap_row)
+{
+    const int gl = glane();
+    int carry = 0;
+#pragma unroll
+    for (int m = 0; m < kARegs; m++) {
+        if (m * kGroup >= na) break;
+        const int k = m * kGroup + gl;
+        const int sa = a[m].x, ea = a[m].y;
+        int c = 0, j0 = 0;
+        if (k < na) {
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
+            }
+            j0 = lo;
+            for (int j = j0; j < nb && sB[j].x < ea; j++) c++;
+        }
+        const int inc = group_incl_scan(c);
+        long long idx = carry + inc - c;
+        for (int j = j0; j < j0 + c; j++, idx++) {
+            const int2 b = sB[j];
+            if (idx < cap_row) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
+        }
+        carry += group_last(inc);
     }
     return carry;
 }
@@ -377,8 +441,9 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
                                                       int *__restrict__ out_runs, long long cap_row,
                                                       unsigned long long *trace)
 {
+    __shared__ int2 stage[kGroupsPerBlock][kStageRuns];
     const int NB = NA - K;
-    const long long t = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    const long long t = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (t >= (long long)P * NB) return;     // whole group
     const int gl = glane();
     const int page = (int)(t / NB), r = (int)(t - (long long)page * NB);
@@ -420,7 +485,25 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     row_span(in, (long long)page * real + ib, bb, nb);
     const int *A = in.runs + 2 * ba;
     const int *B = in.runs + 2 * bb;
-    const int cnt = group_intersect(A, na, B, nb, o, cap_row);
+    int cnt;
+    if (na <= kStageRuns && nb <= kStageRuns) {
+        const int2 *A2 = (const int2 *)A, *B2 = (const int2 *)B;
+        int2 a[kARegs], b[kARegs];
+#pragma unroll
+        for (int m = 0; m < kARegs; m++) {
+            const int k = m * kGroup + gl;
+            a[m] = k < na ? A2[k] : make_int2(0, 0);
+            b[m] = k < nb ? B2[k] : make_int2(0, 0);
+        }
+        int2 *sB = stage[threadIdx.x >> 4];
+#pragma unroll
+        for (int m = 0; m < kARegs; m++)
+            if (m * kGroup + gl < nb) sB[m * kGroup + gl] = b[m];
+        wave_lds_sync();
+        cnt = group_intersect_staged(a, na, sB, nb, (int2 *)o, cap_row);
+    } else {
+        cnt = group_intersect(A, na, B, nb, o, cap_row);
+    }
     if (gl == 0) {
         out_cnt[t] = (int)min((long long)cnt, cap_row);
         if (trace) trace_add(trace, (unsigned long long)(na + (r + K >= NB ? nb : 0)), (unsigned long long)cnt);
@@ -432,7 +515,7 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
 // first or last one.
 __global__ __launch_bounds__(256) void gap_count_kernel(RowsIn in, int R, int W, int *__restrict__ counts)
 {
-    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long r = (long long)xcd_block() * 256 + threadIdx.x;
     if (r >= R) return;
     long long base;
     int n;
@@ -450,7 +533,7 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
                                                         int *__restrict__ out_runs, long long cap,
                                                         unsigned long long *trace)
 {
-    const long long r = (long long)blockIdx.x * kGroupsPerBlock + (threadIdx.x >> 4);
+    const long long r = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= R) return;
     const int gl = glane();
     long long base;
@@ -578,7 +661,7 @@ static RleWs rle_layout(void *base, int32_t W, int32_t rows, int32_t H, morph_se
     const long long P = rows / H;
     RleWs L{};
     L.rows_max = P * (H + (long long)se.h - 1);
-    L.cap_row = (W + 1) / 2;
+    L.cap_row = ((W + 1) / 2 + 15) & ~15LL;      // slot rows start on 128-byte lines
     char *p = (char *)base;
     size_t off = 0;
     auto take = [&](size_t b) { int *q = p ? (int *)(p + off) : nullptr; off += r256(b); return q; };
