@@ -338,7 +338,7 @@ def main():
     n_ops = len(packed_jobs)
     px_step = (n_ops * B * page_px if do_packed else 0) + (n_ops * B * page_px if do_rle else 0)
     out = {
-        "metric": "Gpixel/s rect erode/dilate/open/close (packed & RLE), letter pages",
+        "metric": "Gpixel/s rect erode/dilate (packed & RLE), % HBM peak; p50/p99 page latency",
         "value": px_step / (dt / args.steps) / 1e9,
         "unit": "Gpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
