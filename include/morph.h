@@ -78,7 +78,7 @@ typedef struct ihipStream_t *morph_stream_t;   /* a hipStream_t; NULL = default 
 
 enum {
     MORPH_OK = 0,
-    MORPH_E_INVAL = -1,          /* null pointer, non-positive size, bad element, bad stride */
+    MORPH_E_INVAL = -1,          /* null or misaligned pointer, non-positive size, bad element, bad stride */
     MORPH_E_SHAPE = -2,          /* dst and src sizes differ */
     MORPH_E_ALIAS = -3,          /* dst memory overlaps src memory */
     MORPH_E_WORKSPACE = -4,      /* workspace smaller than morph_workspace_bytes() */
@@ -101,7 +101,7 @@ typedef struct {
     int32_t width, height;
     int32_t npages;                      /* >= 1 */
     int32_t *row_ptr;                    /* npages*height + 1 entries */
-    int32_t *runs;                       /* 2*capacity entries */
+    int32_t *runs;                       /* 2*capacity entries, 8-byte aligned */
     int64_t capacity;
 } morph_rle_t;
 

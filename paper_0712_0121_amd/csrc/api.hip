@@ -479,6 +479,7 @@ static bool rle_ok(const morph_rle_t *r)
     if (!r || !r->row_ptr) return false;
     if (r->width < 1 || r->height < 1 || r->npages < 1 || r->capacity < 0) return false;
     if (r->capacity > 0 && !r->runs) return false;
+    if (((uintptr_t)r->runs) & 7 || ((uintptr_t)r->row_ptr) & 3) return false;   // runs are read as pairs
     if ((long long)r->height * r->npages >= 0x7fffffffLL) return false;
     return true;
 }

@@ -266,6 +266,10 @@ __device__ __forceinline__ void row_span(const RowsIn &v, long long r, long long
 
 constexpr int kGroup = 16;                        // lanes that share one row
 constexpr int kGroupsPerBlock = 256 / kGroup;
+// Rows of up to kStageRuns runs are loaded whole before they are used: into
+// registers (kARegs runs per lane) or a per-group LDS window.
+constexpr int kStageRuns = 128;
+constexpr int kARegs = kStageRuns / kGroup;
 
 __device__ __forceinline__ int glane() { return (int)(threadIdx.x & (kGroup - 1)); }
 
@@ -286,6 +290,12 @@ __device__ __forceinline__ int group_incl_scan(int x)
     x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);    // row_shr:4
     x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);    // row_shr:8
     return x;
+}
+
+// Lane 0 of this lane's group (DPP row_newbcast:0).
+__device__ __forceinline__ int group_first(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xf, 0xf, false);
 }
 
 // Lane 15 of this lane's group (DPP row_newbcast:15).
@@ -317,28 +327,60 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
     const int right = w - 1 - cx;
     int *o = out_runs + 2 * r * cap_row;
     int carry = 0;
-    for (int k0 = 0; k0 < ncand; k0 += kGroup) {
-        const int k = k0 + gl;
-        int s = 0, e = 0;
-        if (k < ncand) {
-            if (comp_in) {
-                s = (k == 0) ? 0 : rr[2 * k - 1];
-                e = (k == n) ? W : rr[2 * k];
-            } else {
-                s = rr[2 * k];
-                e = rr[2 * k + 1];
-            }
-        }
+    // candidate k -> kept run (ns, ne) at the next free slot
+    auto emit = [&](int k, int s, int e) {
         const int ns = (s == 0) ? 0 : s + cx;
         const int ne = (e == W) ? W : e - right;
         const bool keep = k < ncand && s < e && ns < ne;
         const unsigned gm = group_ballot(keep);
         const int idx = carry + __popc(gm & ((1u << gl) - 1));
-        if (keep && idx < cap_row) {
-            o[2 * idx] = ns;
-            o[2 * idx + 1] = ne;
-        }
+        if (keep && idx < cap_row) ((int2 *)o)[idx] = make_int2(ns, ne);
         carry += __popc(gm);
+    };
+    if (ncand <= kStageRuns) {
+        // the whole row in registers (lane k holds runs k + 16 m), every load
+        // issued before the first use
+        const int2 *r2 = (const int2 *)rr;
+        int2 v[kARegs];
+#pragma unroll
+        for (int m = 0; m < kARegs; m++) {
+            const int k = m * kGroup + gl;
+            v[m] = k < n ? r2[k] : make_int2(0, 0);
+        }
+        int prev_end = 0;                   // end of run 16 m - 1
+#pragma unroll
+        for (int m = 0; m < kARegs; m++) {
+            if (m * kGroup >= ncand) break;
+            const int k = m * kGroup + gl;
+            int s, e;
+            if (comp_in) {
+                // gap k lies between the end of run k - 1 (the lane before,
+                // or lane 15 of the previous block) and the start of run k
+                const int pe = __builtin_amdgcn_update_dpp(prev_end, v[m].y, 0x111, 0xf, 0xf, false);
+                s = (k == 0) ? 0 : pe;
+                e = (k == n) ? W : v[m].x;
+                prev_end = group_last(v[m].y);
+            } else {
+                s = v[m].x;
+                e = v[m].y;
+            }
+            emit(k, s, e);
+        }
+    } else {
+        for (int k0 = 0; k0 < ncand; k0 += kGroup) {
+            const int k = k0 + gl;
+            int s = 0, e = 0;
+            if (k < ncand) {
+                if (comp_in) {
+                    s = (k == 0) ? 0 : rr[2 * k - 1];
+                    e = (k == n) ? W : rr[2 * k];
+                } else {
+                    s = rr[2 * k];
+                    e = rr[2 * k + 1];
+                }
+            }
+            emit(k, s, e);
+        }
     }
     if (gl == 0) {
         out_cnt[r] = (int)min((long long)carry, cap_row);
@@ -389,8 +431,6 @@ __device__ __forceinline__ int group_intersect(const int *A, int na, const int *
 // of A) and row B staged in this group's LDS window.  Every load of both
 // rows has been issued before the first search step, so a group waits for
 // global memory twice (counts, then runs) instead of once per search step.
-constexpr int kStageRuns = 128;                 // runs of a row a group stages
-constexpr int kARegs = kStageRuns / kGroup;     // runs of row A per lane
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -409,16 +449,16 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
         if (m * kGroup >= na) break;
         const int k = m * kGroup + gl;
         const int sa = a[m].x, ea = a[m].y;
-        int c = 0, j0 = 0;
-        if (k < na) {
-            int lo = 0, hi = nb;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
-            }
-            j0 = lo;
-            for (int j = j0; j < nb && sB[j].x < ea; j++) c++;
+        // j0 = the first run of B that ends after sa starts (ends ascend)
+        int lo = 0, hi = nb;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
         }
+        const int j0 = lo;
+        int c = 0;
+        if (k < na)
+            for (int j = j0; j < nb && sB[j].x < ea; j++) c++;
         const int inc = group_incl_scan(c);
         long long idx = carry + inc - c;
         for (int j = j0; j < j0 + c; j++, idx++) {
@@ -485,24 +525,31 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     row_span(in, (long long)page * real + ib, bb, nb);
     const int *A = in.runs + 2 * ba;
     const int *B = in.runs + 2 * bb;
-    int cnt;
-    if (na <= kStageRuns && nb <= kStageRuns) {
-        const int2 *A2 = (const int2 *)A, *B2 = (const int2 *)B;
+    // the intersection is symmetric: the shorter row goes to registers and
+    // its runs to the lanes, the longer one is searched
+    const bool swap = nb < na;
+    const int *S = swap ? B : A, *L = swap ? A : B;
+    const int ns = min(na, nb), nl = max(na, nb);
+    int cnt = 0;
+    if (ns == 0) {
+        cnt = 0;
+    } else if (nl <= kStageRuns) {
+        const int2 *S2 = (const int2 *)S, *L2 = (const int2 *)L;
         int2 a[kARegs], b[kARegs];
 #pragma unroll
         for (int m = 0; m < kARegs; m++) {
             const int k = m * kGroup + gl;
-            a[m] = k < na ? A2[k] : make_int2(0, 0);
-            b[m] = k < nb ? B2[k] : make_int2(0, 0);
+            a[m] = k < ns ? S2[k] : make_int2(0, 0);
+            b[m] = k < nl ? L2[k] : make_int2(0, 0);
         }
         int2 *sB = stage[threadIdx.x >> 4];
 #pragma unroll
         for (int m = 0; m < kARegs; m++)
-            if (m * kGroup + gl < nb) sB[m * kGroup + gl] = b[m];
+            if (m * kGroup + gl < nl) sB[m * kGroup + gl] = b[m];
         wave_lds_sync();
-        cnt = group_intersect_staged(a, na, sB, nb, (int2 *)o, cap_row);
+        cnt = group_intersect_staged(a, ns, sB, nl, (int2 *)o, cap_row);
     } else {
-        cnt = group_intersect(A, na, B, nb, o, cap_row);
+        cnt = group_intersect(S, ns, L, nl, o, cap_row);
     }
     if (gl == 0) {
         out_cnt[t] = (int)min((long long)cnt, cap_row);
@@ -542,8 +589,45 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
     const int *rr = in.runs + 2 * base;
     const long long o = row_ptr[r];
     const int nout = row_ptr[r + 1] - row_ptr[r];
-    const int skip = (comp && n > 0 && rr[0] == 0) ? 1 : 0;
     if (trace && gl == 0) trace_add(trace, (unsigned long long)n, (unsigned long long)nout);
+    if ((comp ? n + 1 : n) <= kStageRuns) {
+        // the whole row in registers (lane k holds runs k + 16 m)
+        const int2 *r2 = (const int2 *)rr;
+        int2 v[kARegs];
+#pragma unroll
+        for (int m = 0; m < kARegs; m++) {
+            const int k = m * kGroup + gl;
+            v[m] = k < n ? r2[k] : make_int2(0, 0);
+        }
+        const int skip = (comp && n > 0 && group_first(v[0].x) == 0) ? 1 : 0;
+        int prev_end = 0;                   // end of run 16 m - 1
+#pragma unroll
+        for (int m = 0; m < kARegs; m++) {
+            if (m * kGroup >= nout) break;
+            const int k = m * kGroup + gl;
+            int s, e;
+            if (!comp) {
+                s = v[m].x;
+                e = v[m].y;
+            } else if (!skip) {
+                // gap k: end of run k - 1 (lane before), start of run k
+                const int pe = __builtin_amdgcn_update_dpp(prev_end, v[m].y, 0x111, 0xf, 0xf, false);
+                s = (k == 0) ? 0 : pe;
+                e = (k == n) ? W : v[m].x;
+            } else {
+                // gap k + 1: end of run k, start of run k + 1 (lane after,
+                // or lane 0 of the next block)
+                const int nf = (m + 1 < kARegs) ? group_first(v[m + 1 < kARegs ? m + 1 : m].x) : 0;
+                const int nx = __builtin_amdgcn_update_dpp(nf, v[m].x, 0x101, 0xf, 0xf, false);
+                s = v[m].y;
+                e = (k + 1 == n) ? W : nx;
+            }
+            prev_end = group_last(v[m].y);
+            if (k < nout && o + k < cap) ((int2 *)out_runs)[o + k] = make_int2(s, e);
+        }
+        return;
+    }
+    const int skip = (comp && n > 0 && rr[0] == 0) ? 1 : 0;
     for (int k = gl; k < nout; k += kGroup) {
         int s, e;
         if (comp) {
@@ -554,10 +638,7 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
             s = rr[2 * k];
             e = rr[2 * k + 1];
         }
-        if (o + k < cap) {
-            out_runs[2 * (o + k)] = s;
-            out_runs[2 * (o + k) + 1] = e;
-        }
+        if (o + k < cap) ((int2 *)out_runs)[o + k] = make_int2(s, e);
     }
 }
 

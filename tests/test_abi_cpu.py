@@ -106,7 +106,7 @@ def test_packed_argument_errors(op):
 
 
 def rle(buf, W, H, cap, npages=1, rp_off=0, runs_off=None):
-    runs_off = (H * npages + 1) * 4 + 64 if runs_off is None else runs_off
+    runs_off = ((H * npages + 1) * 4 + 64 + 7) & ~7 if runs_off is None else runs_off
     return M.morph_rle_t(W, H, npages, buf.ptr + rp_off, buf.ptr + runs_off, cap)
 
 
@@ -126,6 +126,7 @@ def test_rle_argument_errors(op):
     need = M.morph_rle_workspace_bytes(op, W, H, 1, (5, 5, 2, 2))
     assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, HostBuf(16).ptr, need - 1) == -4
     assert call(rle(a, W, H, -1), rle(b, W, H, cap)) == -1
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap, runs_off=4 * (H + 1) + 64)) == -1   # runs not 8-byte aligned (188)
     # addresses 1 TiB apart, never dereferenced: the size check comes first
     huge_a = M.morph_rle_t(100000, 60000, 1, 1 << 40, (1 << 40) + (1 << 30), 10**10)
     huge_b = M.morph_rle_t(100000, 60000, 1, 2 << 40, (2 << 40) + (1 << 30), 10**10)
