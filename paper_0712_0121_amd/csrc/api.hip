@@ -506,7 +506,7 @@ static int rect_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, morp
         return MORPH_E_SHAPE;
     if (rle_alias(dst, src)) return MORPH_E_ALIAS;
     const long long ext = (long long)src->npages * (src->height + (long long)se.h - 1);
-    if (ext * ((src->width + 1) / 2) >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    if (ext * ((((long long)src->width + 1) / 2 + 15) & ~15LL) >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
     if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
     const size_t need = rle_op_workspace(op, src->width, src->height * src->npages, src->height, se);
     if (!ws || ws_bytes < need) return MORPH_E_WORKSPACE;
@@ -579,6 +579,8 @@ int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_s
     if (overlap(src->row_ptr, rle_extent_rp(src), dst->words, ext) ||
         (src->capacity && overlap(src->runs, rle_extent_runs(src), dst->words, ext)))
         return MORPH_E_ALIAS;
+    // one thread per output word, indexed in 32 bits
+    if ((long long)dst->height * dst->npages * ((dst->width + 63) / 64) >= 0xffffffffLL) return MORPH_E_UNSUPPORTED;
     hipError_t e = rle_to_packed(*dst, *src, (hipStream_t)stream);
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
     return MORPH_OK;

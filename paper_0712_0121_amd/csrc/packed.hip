@@ -252,16 +252,17 @@ __device__ __forceinline__ void take_loads(const RectPage &P, const Tile &T, uin
 // (issued, not yet waited for).  Before the last row pass, which needs only
 // LDS, the loads of the next tile are issued into reg, so they are in flight
 // while this tile finishes.
-template <class GetNext>
+template <int NST, class GetNext>
 __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, uint64_t (&reg)[CM],
                                              uint64_t *lds, GetNext get_next)
 {
     bool more = false;
     const int tid = threadIdx.x;
-    const int nst = P.nst;
+    constexpr int nst = NST;
     int NRs = T.NR;
     int gy0 = T.gy0;
     const int TWp = T.TWp;
+#pragma unroll
     for (int s = 0; s < nst; s++) {
         const Stage S = (s == 0) ? P.st[0] : P.st[1];
         const bool last = s + 1 == nst;
@@ -413,14 +414,9 @@ __device__ __forceinline__ void tile_coords(const RectPage &P, int t, int &page,
 // One operation over all tiles of npages pages: a persistent grid, each
 // workgroup taking every nx-th tile of its XCD's range.  Tile coordinates
 // advance by carries, without divisions in the loop.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void rect_kernel(RectPage Parg,
-                                                                                              int ntiles)
+template <int NST>
+__device__ __forceinline__ void rect_loop(const RectPage &P, uint64_t *lds, int ntiles)
 {
-    __shared__ __align__(16) uint64_t lds[kLdsWords];
-    // the page parameters are read from the argument segment where they are
-    // used, rather than all held in scalar registers for the whole kernel
-    (void)Parg;
-    const RectPage &P = *(const RectPage *)__builtin_amdgcn_kernarg_segment_ptr();
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int x = b & 7, nx = (G - x + 7) >> 3;
     const int q = ntiles >> 3, rem = ntiles & 7;
@@ -446,13 +442,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             issue_loads(P, make_tile(P, np, nbd, nst), r);
             return true;
         };
-        if (!process_tile(P, make_tile(P, page, band, strip), reg, lds, get_next)) break;
+        if (!process_tile<NST>(P, make_tile(P, page, band, strip), reg, lds, get_next)) break;
         k += nx;
         page = np;
         band = nbd;
         strip = nst;
         lds_barrier();
     }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void rect_kernel(RectPage Parg,
+                                                                                              int ntiles)
+{
+    __shared__ __align__(16) uint64_t lds[kLdsWords];
+    // the page parameters are read from the argument segment where they are
+    // used, rather than all held in scalar registers for the whole kernel
+    (void)Parg;
+    const RectPage &P = *(const RectPage *)__builtin_amdgcn_kernarg_segment_ptr();
+    if (P.nst == 1)
+        rect_loop<1>(P, lds, ntiles);
+    else
+        rect_loop<2>(P, lds, ntiles);
 }
 
 // A batch of pages with their own operations: workgroups take tiles from a
@@ -493,7 +503,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const RectPage &P = pages[__builtin_amdgcn_readfirstlane(tr.page)];
         const Tile T = make_tile(P, 0, __builtin_amdgcn_readfirstlane(tr.band),
                                  __builtin_amdgcn_readfirstlane(tr.strip));
-        if (!process_tile(P, T, reg, lds, get_next)) break;
+        const bool more = P.nst == 1 ? process_tile<1>(P, T, reg, lds, get_next)
+                                     : process_tile<2>(P, T, reg, lds, get_next);
+        if (!more) break;
         t = tn;
         parity ^= 1;
         lds_barrier();

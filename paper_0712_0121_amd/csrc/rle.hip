@@ -210,26 +210,29 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
 // -------------------------------------------------------- runs -> packed
 // One thread per output word: binary search for the first run ending after
 // the word's first pixel, then OR in every run that starts before its end.
+// The host launches it only while rows x words stays below 2^32.
 __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict__ row_ptr,
                                                           const int *__restrict__ runs, int nw,
                                                           int R, int H, uint64_t *__restrict__ words,
-                                                          int stride, long long page_words,
+                                                          int stride, long long page_words, long long cap,
                                                           unsigned long long *trace)
 {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (long long)R * nw) return;
-    const int r = (int)(t / nw), j = (int)(t - (long long)r * nw);
+    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= (unsigned)R * (unsigned)nw) return;
+    const int r = (int)(t / (unsigned)nw), j = (int)(t - (unsigned)r * (unsigned)nw);
     const int page = r / H, y = r - page * H;
-    int lo = row_ptr[r];
-    int hi = row_ptr[r + 1];
+    // offsets clamped to the run array, so a damaged row_ptr cannot send
+    // the reads outside it
+    const int b0 = (int)min((long long)max(row_ptr[r], 0), cap);
+    const int b1 = (int)max((long long)b0, min((long long)row_ptr[r + 1], cap));
     const int x0 = 64 * j, x1 = x0 + 64;
+    int lo = b0, hi = b1;
     while (lo < hi) {                      // first run with end > x0
         const int mid = (lo + hi) >> 1;
         if (runs[2 * mid + 1] > x0) hi = mid; else lo = mid + 1;
     }
     uint64_t v = 0;
-    const int end = row_ptr[r + 1];
-    for (int k = lo; k < end; k++) {
+    for (int k = lo; k < b1; k++) {
         const int s = runs[2 * k], e = runs[2 * k + 1];
         if (s >= x1) break;
         const int a = max(s, x0) - x0, b = min(e, x1) - x0;   // 0 <= a < b <= 64
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
         v |= hiMask & ~((1ull << a) - 1);
     }
     words[(long long)page * page_words + (long long)y * stride + j] = v;
-    if (trace && j == 0) trace_add(trace, (unsigned long long)(row_ptr[r + 1] - row_ptr[r]), 0);
+    if (trace && j == 0) trace_add(trace, (unsigned long long)(b1 - b0), 0);
 }
 
 // ------------------------------------------------- rows in two layouts
@@ -440,7 +443,7 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], int na, const int2 *sB, int nb,
-                                                      int2 *o, long long cap_row)
+                                                      int2 *__restrict__ o, int cap)
 {
     const int gl = glane();
     int carry = 0;
@@ -460,10 +463,11 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
         if (k < na)
             for (int j = j0; j < nb && sB[j].x < ea; j++) c++;
         const int inc = group_incl_scan(c);
-        long long idx = carry + inc - c;
-        for (int j = j0; j < j0 + c; j++, idx++) {
-            const int2 b = sB[j];
-            if (idx < cap_row) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
+        const int idx = carry + inc - c;
+        const int lim = min(c, cap - idx);          // never past the slot row
+        for (int q = 0; q < lim; q++) {
+            const int2 b = sB[j0 + q];
+            o[idx + q] = make_int2(max(sa, b.x), min(ea, b.y));
         }
         carry += group_last(inc);
     }
@@ -486,7 +490,9 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     const long long t = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (t >= (long long)P * NB) return;     // whole group
     const int gl = glane();
-    const int page = (int)(t / NB), r = (int)(t - (long long)page * NB);
+    // the host keeps every row index below 2^31: 32-bit division
+    const unsigned tu = (unsigned)t;
+    const int page = (int)(tu / (unsigned)NB), r = (int)(tu - (unsigned)page * (unsigned)NB);
     const int ia = r - off, ib = r + K - off;
     const bool va = ia >= 0 && ia < real, vb = ib >= 0 && ib < real;
     int *o = out_runs + 2 * t * cap_row;
@@ -547,7 +553,7 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
         for (int m = 0; m < kARegs; m++)
             if (m * kGroup + gl < nl) sB[m * kGroup + gl] = b[m];
         wave_lds_sync();
-        cnt = group_intersect_staged(a, ns, sB, nl, (int2 *)o, cap_row);
+        cnt = group_intersect_staged(a, ns, sB, nl, (int2 *)o, (int)cap_row);
     } else {
         cnt = group_intersect(S, ns, L, nl, o, cap_row);
     }
@@ -715,12 +721,13 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
 {
     const int R = src.height * src.npages;
     const int nw = (src.width + 63) / 64;
-    const long long total = (long long)R * nw;
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_RLE_TO_PACK, s);
-    hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, src.row_ptr,
-                       src.runs, nw, R, src.height, dst.words, dst.stride_words,
-                       (long long)dst.stride_words * dst.height, trace_block(tr, MORPH_K_RLE_TO_PACK));
+    if ((long long)R * nw >= 0xffffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for((long long)R * nw, 256)), dim3(256), 0, s,
+                       src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
+                       (long long)dst.stride_words * dst.height, (long long)src.capacity,
+                       trace_block(tr, MORPH_K_RLE_TO_PACK));
     trace_after(MORPH_K_RLE_TO_PACK, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
