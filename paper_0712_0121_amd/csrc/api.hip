@@ -70,8 +70,12 @@ struct Launch {
 
 // Groups passes into launches (two per launch when a tile fits both) and
 // fills in complement flags and tile shapes.  Buffers are set by the caller.
+// With small_tiles, a one-stage launch whose halo rows stay under a fifth
+// of a small tile runs four 256-thread workgroups per CU instead of two
+// 512-thread ones (measured a few percent faster for short elements; the
+// number of launches does not change).
 static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int tile_rows,
-                          int strip_words, std::vector<Launch> &out)
+                          int strip_words, std::vector<Launch> &out, bool small_tiles = false)
 {
     const std::vector<Pass> ps = op_passes(op, se);
     const int nw = (W + 63) / 64;
@@ -99,6 +103,12 @@ static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int t
             p.nst = 1;
             p.st[0] = ps[i].st;
             if (!plan_tiles(p, tile_rows, strip_words, npages)) return false;
+        }
+        if (small_tiles && tile_rows == 0 && strip_words == 0 && p.nst == 1) {
+            int hsum = 0;
+            for (int k = 0; k < p.nst; k++) hsum += p.st[k].h - 1;
+            RectPage q = p;
+            if (plan_tiles(q, 0, 0, npages, kThreadsSmall) && q.TR >= 32 && 5 * hsum <= q.TR) p = q;
         }
         const size_t last = i + p.nst - 1;
         const int out_dom = (last + 1 < ps.size()) ? ps[last + 1].dom : 0;
@@ -151,7 +161,7 @@ static int rect_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *
         return MORPH_E_SHAPE;
     if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
     std::vector<Launch> L;
-    if (!plan_launches(op, se, src->width, src->height, src->npages, 0, 0, L))
+    if (!plan_launches(op, se, src->width, src->height, src->npages, 0, 0, L, true))
         return MORPH_E_UNSUPPORTED;
     const int W = src->width, H = src->height, P = src->npages, nw = (W + 63) / 64;
     const size_t img = round256(image_bytes(W, H * P));
@@ -285,7 +295,7 @@ static int build_batch(const morph_page_desc_t *descs, int32_t n, std::vector<Re
             L.size() != 1)
             return MORPH_E_UNSUPPORTED;
         RectPage p = L[0].p;
-        if (!tile_fits(p)) return MORPH_E_UNSUPPORTED;
+        if (p.nt != kThreads || !tile_fits(p)) return MORPH_E_UNSUPPORTED;
         p.src = d.src.words;
         p.dst = d.dst.words;
         p.sstride = d.src.stride_words;

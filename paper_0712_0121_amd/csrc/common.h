@@ -11,8 +11,12 @@ namespace morph {
 
 // ------------------------------------------------------------------ packed
 // Geometry of the fused band kernel (one workgroup = one tile).
-constexpr int kThreads = 512;          // threads per workgroup
+constexpr int kThreads = 512;          // threads per workgroup (large tiles)
 constexpr int kLdsWords = 10236;       // ~80 KiB of LDS per workgroup (two per CU, with room for a queue slot)
+constexpr int kThreadsSmall = 256;     // threads per workgroup (small tiles: four workgroups per CU)
+constexpr int kLdsWordsSmall = 5116;   // ~40 KiB of LDS per small-tile workgroup
+
+constexpr int lds_words_for(int nt) { return nt == kThreadsSmall ? kLdsWordsSmall : kLdsWords; }
 constexpr int kChunkMax = 16;          // rows a thread keeps in registers in the column pass
 constexpr int kWordsPerItem = 4;       // consecutive words one row-pass item produces
 constexpr int kItemsMax = 4;           // row-pass items a thread holds across a barrier
@@ -36,13 +40,15 @@ struct RectPage {
     Stage st[2];
     int in_c, mid_c, out_c;   // complement the input / between stages / the output (0 or 1)
     int TR, SW;               // tile rows, strip words
+    int nt;                   // threads per workgroup: kThreads or kThreadsSmall
     int nbands, nstrips;
     uint64_t padmask;         // valid bits of the last word of a row
     long long src_page_words, dst_page_words;  // stacked pages
 };
 
-// Tile planning (host).  Returns false if no tile shape fits.
-bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages);
+// Tile planning (host) for workgroups of nt threads.  Returns false if no
+// tile shape fits.
+bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages, int nt = kThreads);
 bool tile_fits(const RectPage &p);
 
 // Launch one fused pass over npages stacked pages.

@@ -252,7 +252,7 @@ __device__ __forceinline__ void take_loads(const RectPage &P, const Tile &T, uin
 // (issued, not yet waited for).  Before the last row pass, which needs only
 // LDS, the loads of the next tile are issued into reg, so they are in flight
 // while this tile finishes.
-template <int NST, class GetNext>
+template <int NST, int NT, class GetNext>
 __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, uint64_t (&reg)[CM],
                                              uint64_t *lds, GetNext get_next)
 {
@@ -306,12 +306,12 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
         const int o_lo = c_lo + 1, o_hi = T.TW - 1 - s;
         const int G = (o_hi - o_lo + WPT - 1) / WPT;
         const int items = NRo * G;
-        const int dr = kThreads / G, dg = kThreads - (kThreads / G) * G;
+        const int dr = NT / G, dg = NT - (NT / G) * G;
         if (last) {
             more = get_next(reg);           // issues the next tile's loads into reg
             const uint64_t inv = P.out_c ? kOnes : 0ull;
             int r = tid / G, g = tid - (tid / G) * G;
-            for (int q = tid; q < items; q += kThreads) {
+            for (int q = tid; q < items; q += NT) {
                 const int c0 = o_lo + g * WPT;
                 uint64_t X[WPT + 2];
                 load_group(lds + r * TWp, c0, X);
@@ -351,7 +351,7 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
             int r = tid / G, g = tid - (tid / G) * G;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
-                if (tid + k * kThreads < items) {
+                if (tid + k * NT < items) {
                     const int c0 = o_lo + g * WPT;
                     uint64_t X[WPT + 2];
                     load_group(lds + r * TWp, c0, X);
@@ -372,7 +372,7 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
             const uint64_t minv = P.mid_c ? kOnes : 0ull;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
-                if (tid + k * kThreads < items) {
+                if (tid + k * NT < items) {
                     const int c0 = o_lo + g * WPT;
                     const int gy = gyo + r;
                     const bool rowin = gy >= 0 && gy < P.H;
@@ -414,7 +414,7 @@ __device__ __forceinline__ void tile_coords(const RectPage &P, int t, int &page,
 // One operation over all tiles of npages pages: a persistent grid, each
 // workgroup taking every nx-th tile of its XCD's range.  Tile coordinates
 // advance by carries, without divisions in the loop.
-template <int NST>
+template <int NST, int NT>
 __device__ __forceinline__ void rect_loop(const RectPage &P, uint64_t *lds, int ntiles)
 {
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
@@ -442,7 +442,7 @@ __device__ __forceinline__ void rect_loop(const RectPage &P, uint64_t *lds, int 
             issue_loads(P, make_tile(P, np, nbd, nst), r);
             return true;
         };
-        if (!process_tile<NST>(P, make_tile(P, page, band, strip), reg, lds, get_next)) break;
+        if (!process_tile<NST, NT>(P, make_tile(P, page, band, strip), reg, lds, get_next)) break;
         k += nx;
         page = np;
         band = nbd;
@@ -451,18 +451,18 @@ __device__ __forceinline__ void rect_loop(const RectPage &P, uint64_t *lds, int 
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void rect_kernel(RectPage Parg,
-                                                                                              int ntiles)
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void rect_kernel(RectPage Parg, int ntiles)
 {
-    __shared__ __align__(16) uint64_t lds[kLdsWords];
+    __shared__ __align__(16) uint64_t lds[lds_words_for(NT)];
     // the page parameters are read from the argument segment where they are
     // used, rather than all held in scalar registers for the whole kernel
     (void)Parg;
     const RectPage &P = *(const RectPage *)__builtin_amdgcn_kernarg_segment_ptr();
     if (P.nst == 1)
-        rect_loop<1>(P, lds, ntiles);
+        rect_loop<1, NT>(P, lds, ntiles);
     else
-        rect_loop<2>(P, lds, ntiles);
+        rect_loop<2, NT>(P, lds, ntiles);
 }
 
 // A batch of pages with their own operations: workgroups take tiles from a
@@ -503,8 +503,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const RectPage &P = pages[__builtin_amdgcn_readfirstlane(tr.page)];
         const Tile T = make_tile(P, 0, __builtin_amdgcn_readfirstlane(tr.band),
                                  __builtin_amdgcn_readfirstlane(tr.strip));
-        const bool more = P.nst == 1 ? process_tile<1>(P, T, reg, lds, get_next)
-                                     : process_tile<2>(P, T, reg, lds, get_next);
+        const bool more = P.nst == 1 ? process_tile<1, kThreads>(P, T, reg, lds, get_next)
+                                     : process_tile<2, kThreads>(P, T, reg, lds, get_next);
         if (!more) break;
         t = tn;
         parity ^= 1;
@@ -543,25 +543,28 @@ int device_cu_count()
 static int max_rows(const RectPage &p, int TW)
 {
     const int TWp = TW + (TW & 1);
-    int nr = ((kLdsWords - 8) / TWp) / kChunkMax * kChunkMax;
+    const int nthreads = p.nt;
+    int nr = ((lds_words_for(p.nt) - 8) / TWp) / kChunkMax * kChunkMax;
     int drop = 0;                   // rows consumed before stage s
     for (int s = 0; s < p.nst; s++) {
         const int ncols = TW - 2 * s;
         if (ncols < 3) return 0;
-        const int chunks = kThreads / ncols;
+        const int chunks = nthreads / ncols;
         if (chunks < 1) return 0;
         nr = std::min(nr, chunks * kChunkMax + drop);
         drop += p.st[s].h - 1;
         if (s + 1 < p.nst) {
             const int G = (ncols - 2 + WPT - 1) / WPT;
-            nr = std::min(nr, (kThreads * kItemsMax) / G + drop);
+            nr = std::min(nr, (nthreads * kItemsMax) / G + drop);
         }
     }
     return nr;
 }
 
-bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages)
+bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages, int nt)
 {
+    if (nt != kThreads && nt != kThreadsSmall) return false;
+    p.nt = nt;
     for (int s = 0; s < p.nst; s++) {
         const Stage &S = p.st[s];
         if (S.w < 1 || S.h < 1 || S.cx < 0 || S.cy < 0 || S.cx >= S.w || S.cy >= S.h) return false;
@@ -590,7 +593,7 @@ bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages)
     } else {
         // enough tiles to give every CU two workgroups, without letting the
         // halo rows dominate
-        const long long want = 2LL * device_cu_count();
+        const long long want = (long long)(2 * kThreads / nt) * device_cu_count();
         const long long bands = std::max<long long>(1, want / ((long long)nstrips * std::max(1, npages)));
         const int tr_par = (int)((p.H + bands - 1) / bands);
         const int floor_rows = std::min(trmax, std::max(16, 2 * hsum));
@@ -610,6 +613,8 @@ bool plan_tiles(RectPage &p, int tile_rows, int strip_words, int npages)
 // and the row-pass items a thread holds across a barrier.
 bool tile_fits(const RectPage &p)
 {
+    if (p.nt != kThreads && p.nt != kThreadsSmall) return false;
+    const int nthreads = p.nt;
     if (p.nst < 1 || p.nst > 2 || p.TR < 1 || p.SW < 1 || p.nw < 1 || p.H < 1) return false;
     if (p.nbands != (p.H + p.TR - 1) / p.TR || p.nstrips != (p.nw + p.SW - 1) / p.SW) return false;
     int hsum = 0;
@@ -623,15 +628,15 @@ bool tile_fits(const RectPage &p)
     const int TWp = TW + (TW & 1);
     int NRs = p.TR + hsum;
     const int rows0 = (NRs + kChunkMax - 1) / kChunkMax * kChunkMax;
-    if ((long long)rows0 * TWp + 8 > kLdsWords) return false;
+    if ((long long)rows0 * TWp + 8 > lds_words_for(p.nt)) return false;
     for (int s = 0; s < p.nst; s++) {
         const int ncols = TW - 2 * s;
         if (ncols < 3) return false;
-        if ((NRs + kChunkMax - 1) / kChunkMax > kThreads / ncols) return false;
+        if ((NRs + kChunkMax - 1) / kChunkMax > nthreads / ncols) return false;
         NRs -= p.st[s].h - 1;
         if (NRs < 1) return false;
         if (s + 1 < p.nst &&
-            (long long)NRs * ((ncols - 2 + WPT - 1) / WPT) > (long long)kThreads * kItemsMax)
+            (long long)NRs * ((ncols - 2 + WPT - 1) / WPT) > (long long)nthreads * kItemsMax)
             return false;
     }
     return true;
@@ -642,9 +647,12 @@ hipError_t launch_rect(const RectPage &p, int npages, hipStream_t stream)
     const long long T = (long long)p.nbands * p.nstrips * npages;
     if (T <= 0) return hipSuccess;
     if (!tile_fits(p) || T > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int grid = (int)std::min<long long>(T, 2LL * device_cu_count());
+    const int grid = (int)std::min<long long>(T, (long long)(2 * kThreads / p.nt) * device_cu_count());
     trace_before(MORPH_K_RECT, stream);
-    hipLaunchKernelGGL(rect_kernel, dim3(grid), dim3(kThreads), 0, stream, p, (int)T);
+    if (p.nt == kThreadsSmall)
+        hipLaunchKernelGGL(rect_kernel<kThreadsSmall>, dim3(grid), dim3(kThreadsSmall), 0, stream, p, (int)T);
+    else
+        hipLaunchKernelGGL(rect_kernel<kThreads>, dim3(grid), dim3(kThreads), 0, stream, p, (int)T);
     trace_after(MORPH_K_RECT, stream, 16.0 * p.nw * (double)p.H * npages);
     return hipGetLastError();
 }
