@@ -126,9 +126,15 @@ class Server:
             if err:
                 self._fail(reqs, err)
             moved = True
+        # downloads finish in the order they were queued when the executor
+        # says so (one copy stream): then polling stops at the first one
+        # still in flight
+        in_order = getattr(self.ex, "downloads_in_order", False)
         still = []
-        for r in self.downloading:
-            if r.error is None and self.ex.downloaded(r):
+        for k, r in enumerate(self.downloading):
+            if r.error is not None:
+                continue
+            if self.ex.downloaded(r):
                 res = self.ex.finish(r)
                 r.result = res if self.keep_results else None
                 r.t_done = self.now()
@@ -136,7 +142,10 @@ class Server:
                 self.used -= self.ex.footprint(r)
                 self.completed.append(r)
                 moved = True
-            elif r.error is None:
+            elif in_order:
+                still.extend(x for x in self.downloading[k:] if x.error is None)
+                break
+            else:
                 still.append(r)
         self.downloading = still
         # admission, first come first served
@@ -174,16 +183,20 @@ class Server:
     def drain(self, timeout: float = 60.0):
         end = self.clock() + timeout
         while not self.idle():
-            if not self.step():
-                time.sleep(20e-6)
+            self.step()
             if self.clock() > end:
                 raise TimeoutError("server did not drain")
 
 
 class GpuExecutor:
-    """Runs the server's work on the GPU through the C ABI."""
+    """Runs the server's work on the GPU through the C ABI.  A step with at
+    most `direct_max` pages launches each page's operation directly (no page
+    table to build and copy, which dominates for one or two pages); larger
+    steps use one persistent batched launch."""
 
-    def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4):
+    downloads_in_order = True            # one download stream
+
+    def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4, direct_max=2):
         import torch
         import paper_0712_0121_amd as M
         self.M, self.torch = M, torch
@@ -195,6 +208,7 @@ class GpuExecutor:
         self.staging = [torch.empty(ws_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(staging_slots)]
         self.staging_ev = [None] * staging_slots
         self.slot = 0
+        self.direct_max = direct_max
 
     def footprint(self, r: Request) -> int:
         return 2 * r.H * ((r.W + 63) // 64) * 8
@@ -226,6 +240,15 @@ class GpuExecutor:
                 st["up"] = None
             op, se = r.chain[r.pos]
             items.append((st["nxt"], st["cur"], op, se))
+        if len(items) <= self.direct_max:
+            with torch.cuda.stream(self.compute):
+                for dst, src, op, se in items:
+                    M.PACKED[op](dst, src, se, self.ws)
+                ev = torch.cuda.Event()
+                ev.record(self.compute)
+            for r in reqs:
+                r.state["ev"] = ev
+            return ev
         k = self.slot
         self.slot = (k + 1) % len(self.staging)
         if self.staging_ev[k] is not None:
@@ -320,8 +343,7 @@ def run_trace_served(server: Server, requests, arrivals, timeout=120.0):
         while i < len(order) and arrivals[order[i]] <= now:
             server.submit(requests[order[i]], arrival=float(arrivals[order[i]]))
             i += 1
-        if not server.step():
-            time.sleep(10e-6)
+        server.step()
         if server.clock() > end:
             raise TimeoutError("trace did not finish")
     return server.completed
