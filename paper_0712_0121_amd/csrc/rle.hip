@@ -460,8 +460,15 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
         }
         const int j0 = lo;
         int c = 0;
-        if (k < na)
-            for (int j = j0; j < nb && sB[j].x < ea; j++) c++;
+        if (k < na) {
+            // most runs overlap at most two runs of the other row
+            const int2 b0 = sB[min(j0, nb - 1)], b1 = sB[min(j0 + 1, nb - 1)];
+            const bool h0 = j0 < nb && b0.x < ea;
+            const bool h1 = h0 && j0 + 1 < nb && b1.x < ea;
+            c = (int)h0 + (int)h1;
+            if (h1)
+                for (int j = j0 + 2; j < nb && sB[j].x < ea; j++) c++;
+        }
         const int inc = group_incl_scan(c);
         const int idx = carry + inc - c;
         const int lim = min(c, cap - idx);          // never past the slot row

@@ -96,3 +96,45 @@ def test_batch_equals_per_page_launches():
     for k in (0, 1):
         img, op, se = items[k]
         np.testing.assert_array_equal(dsts[k].to_numpy(), oracle.pack(oracle.sat_apply(op, img, se)))
+
+
+def test_full_mixed_batch_as_timed(tmp_path):
+    """The timed batched workload itself: 256 pages of 1275x1650, 2480x3508,
+    2550x3300 and 5100x6600 with random elements up to 63 x 63, as one
+    persistent launch replayed from a graph, with library-default and with
+    autotuned tiles.  Every fourth page is checked whole against the oracle's
+    summed-area evaluator; every page against its own per-page launch."""
+    from paper_0712_0121_amd.tune import Tuner
+    items = pagegen.mixed_batch(256, seed=3000, pool_per_size=4)
+    words = {}
+    srcs, dsts, dsts_t = [], [], []
+    for it in items:
+        if id(it.page) not in words:
+            words[id(it.page)] = it.page.words()
+        srcs.append(M.Bitmap.from_words(words[id(it.page)], it.page.W))
+        dsts.append(M.Bitmap.empty(it.page.W, it.page.H))
+        dsts_t.append(M.Bitmap.empty(it.page.W, it.page.H))
+    plan = M.BatchPlan([(d, s, it.op, it.se) for it, s, d in zip(items, srcs, dsts)])
+    tuner = Tuner(cache_path=str(tmp_path / "tune.json"))
+    widths = {}
+    for it in items:
+        widths.setdefault(it.page.W, (it.page.H, words[id(it.page)]))
+    tuner.tune_shapes(widths, ops=("erode", "open"), h_values=(5, 40), batch=8)
+    plan_t = M.BatchPlan([(d, s, it.op, it.se) + tuner.params(it.page.W, it.page.H, it.op, it.se)
+                          for it, s, d in zip(items, srcs, dsts_t)])
+    for _ in range(2):                      # two replays, the second over the first's output
+        plan.run(use_graph=True)
+        plan_t.run(use_graph=True)
+    torch.cuda.synchronize()
+    sizes = set()
+    for k, (it, s, d, dt) in enumerate(zip(items, srcs, dsts, dsts_t)):
+        got = d.to_numpy()
+        np.testing.assert_array_equal(dt.to_numpy(), got, err_msg="tuned tiles, page %d" % k)
+        if k % 4 == 0:
+            sizes.add((it.page.W, it.page.H))
+            want = oracle.pack(oracle.sat_apply(it.op, it.page.img, it.se))
+            np.testing.assert_array_equal(got, want, err_msg="page %d %s %s %s" % (k, it.op, it.se, got.shape))
+        single = M.rect_packed(it.op, s, it.se)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(single.to_numpy(), got, err_msg="per-page launch, page %d" % k)
+    assert sizes == set(pagegen.PAGE_SIZES)

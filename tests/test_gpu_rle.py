@@ -192,3 +192,34 @@ def test_trace_counts_launches_and_bytes():
     assert res["col_and_kernel"]["launches"] == 3          # offsets 1, 2, then 1
     assert res["row_erode_kernel"]["launches"] == 1
     assert res["pack_rows_kernel"]["launches"] == 1
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+def test_letter_batch_as_timed(op):
+    """The timed letter workload itself: 256 stacked 2550 x 3300 pages (16
+    distinct, replicated) in one launch per operation, on both paths, with
+    one vertical and one square element.  The 16 distinct pages are checked
+    whole against the oracle's summed-area evaluator, the replicas against
+    them, and bitmap -> runs -> bitmap must give back the packed result."""
+    B, D = 256, 16
+    pool = [pagegen.letter_page(2000 + i) for i in range(D)]
+    W, H = 2550, 3300
+    host = np.concatenate([pool[i % D].words() for i in range(B)])
+    src = M.Bitmap.from_words(host, W, npages=B)
+    del host
+    r_in = M.pack_to_rle(src)
+    for se in [(1, 31, 0, 15), (21, 21, 10, 10)]:
+        pk = M.rect_packed(op, src, se).to_numpy().reshape(B, H, -1)
+        r_out = M.rect_rle(op, r_in, se)
+        back = M.rle_to_pack(r_out).to_numpy().reshape(B, H, -1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(back, pk, err_msg="%s %s: runs vs packed" % (op, se))
+        for i in range(D):
+            want = oracle.pack(oracle.sat_apply(op, pool[i].img, se))
+            np.testing.assert_array_equal(pk[i], want, err_msg="%s %s page %d" % (op, se, i))
+        for i in range(D, B):
+            np.testing.assert_array_equal(pk[i], pk[i % D], err_msg="%s %s replica %d" % (op, se, i))
+        counts = np.diff(r_out.row_ptr.cpu().numpy()).reshape(B, H)
+        for i in range(D, B):
+            np.testing.assert_array_equal(counts[i], counts[i % D])
+        del pk, back, r_out
