@@ -52,6 +52,7 @@ class Request:
     chain: list                    # [(op, (w, h, cx, cy)), ...]
     arrival: float = 0.0           # seconds on the server clock
     pos: int = 0                   # operations queued
+    alone: bool = False            # admitted while the server had nothing else
     t_admit: float = -1.0
     t_done: float = -1.0
     result: object = None
@@ -116,9 +117,10 @@ class Server:
 
         Operations of one request are queued in order on one device stream,
         so the next operation of a request is queued as soon as the previous
-        one has been queued, without waiting for it; a request's download is
-        queued behind its last operation.  At most max_batches launches are
-        outstanding at a time."""
+        one has been queued, without waiting for it (within the same step
+        while launch slots are free); a request's download is queued behind
+        its last operation.  At most max_batches launches are outstanding at
+        a time."""
         moved = False
         while self.batches and self.ex.done(self.batches[0][0]):
             token, reqs = self.batches.popleft()
@@ -154,11 +156,18 @@ class Server:
             self.used += self.ex.footprint(r)
             self.peak_used = max(self.peak_used, self.used)
             r.t_admit = self.now()
+            # nothing else on the device and nothing else waiting: the
+            # executor may keep this request's copies on its compute stream
+            r.alone = not (self.active or self.batches or self.downloading or self.pending)
             self.ex.begin(r)
             self.active.append(r)
             moved = True
-        # the next operation of every admitted request, as one launch
-        if self.active and len(self.batches) < self.max_batches:
+        # the next operation of every admitted request, as one launch; while
+        # launch slots are free, the operation after it too (stream order
+        # keeps each request's operations in sequence), so a request that is
+        # alone has its whole chain queued at once and later arrivals join
+        # the next launch at their own position
+        while self.active and len(self.batches) < self.max_batches:
             ready = list(self.active)
             try:
                 token = self.ex.launch(ready)
@@ -194,7 +203,11 @@ class GpuExecutor:
     table to build and copy, which dominates for one or two pages); larger
     steps use one persistent batched launch."""
 
-    downloads_in_order = True            # one download stream
+    # downloads complete in the order they were queued: they run on the
+    # download stream, except a lone request's, which is admitted only when
+    # no download is pending and whose copy precedes, on the compute stream,
+    # every launch a later download waits for
+    downloads_in_order = True
 
     def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4, direct_max=2):
         import torch
@@ -224,10 +237,15 @@ class GpuExecutor:
             t.record_stream(self.copy)
             t.record_stream(self.compute)
             t.record_stream(self.down)
-        with torch.cuda.stream(self.copy):
+        # a request alone on the device has nothing to overlap with: its
+        # copies go on the compute stream, which saves two cross-stream waits
+        up = self.compute if r.alone else self.copy
+        with torch.cuda.stream(up):
             a.words.copy_(host[:, : a.stride], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.copy)
+            ev = None
+            if up is not self.compute:
+                ev = torch.cuda.Event()
+                ev.record(up)
         r.state = {"cur": a, "nxt": b, "up": ev, "host": host}
 
     def launch(self, reqs):
@@ -275,11 +293,13 @@ class GpuExecutor:
         torch = self.torch
         st = r.state
         out = torch.empty((r.H, st["cur"].stride), dtype=torch.int64, pin_memory=True)
-        with torch.cuda.stream(self.down):
-            self.down.wait_event(st["ev"])
+        down = self.compute if r.alone else self.down
+        with torch.cuda.stream(down):
+            if down is not self.compute:
+                down.wait_event(st["ev"])
             out.copy_(st["cur"].words, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.down)
+            ev.record(down)
         st["out"], st["down"] = out, ev
 
     def downloaded(self, r: Request) -> bool:
