@@ -392,38 +392,75 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
 }
 
 // ----------------------------------------------------- between-line pass
-// Intersection of run lists A (na runs) and B (nb runs) into o, by the
-// lanes of one group: lane k takes runs k, k+16, ... of A, finds the first
-// run of B that ends after it starts, and emits every overlap in order.
-__device__ __forceinline__ int group_intersect(const int *A, int na, const int *B, int nb, int *o,
-                                               long long cap_row)
+// The first doubling step of a chain reads its rows straight from the input
+// and applies the within-line erosion as it reads them (there is no
+// separate within-line launch then).  Candidate k of a row is its run k, or
+// with comp the gap before run k (gap n runs to the right border), shrunk by
+// cx on the left and `right` on the right unless that side lies on a border.
+// A candidate that vanishes keeps s >= e and is skipped; starts and ends
+// still ascend with k, so the searches below need no compaction.
+struct RowX {
+    int cx, right, comp, W;
+};
+
+__device__ __forceinline__ int2 shrink(const RowX &x, int s, int e)
+{
+    return make_int2(s == 0 ? 0 : s + x.cx, e == x.W ? x.W : e - x.right);
+}
+
+__device__ __forceinline__ bool live(int2 c) { return c.x < c.y; }
+
+// Candidate k of a stored row R of n runs (k < n, or k <= n with comp).
+template <bool ROWX>
+__device__ __forceinline__ int2 cand(const RowX &x, const int *R, int n, int k)
+{
+    if (!ROWX) return make_int2(R[2 * k], R[2 * k + 1]);
+    if (x.comp) return shrink(x, k == 0 ? 0 : R[2 * k - 1], k == n ? x.W : R[2 * k]);
+    return shrink(x, R[2 * k], R[2 * k + 1]);
+}
+
+// Intersection of the rows A (na candidates) and B (nb candidates) into o,
+// by the lanes of one group: lane k takes candidates k, k+16, ... of A,
+// finds the first candidate of B that ends after it starts, and emits every
+// overlap with a live candidate in order.
+template <bool ROWX>
+__device__ __forceinline__ int group_intersect(const RowX &x, const int *A, int na_raw, int na, const int *B,
+                                               int nb_raw, int nb, int *o, long long cap_row)
 {
     const int gl = glane();
     int carry = 0;
     for (int k0 = 0; k0 < na; k0 += kGroup) {
         const int k = k0 + gl;
-        int c = 0, j0 = 0, sa = 0, ea = 0;
+        int c = 0, span = 0, j0 = 0, sa = 0, ea = 0;
         if (k < na) {
-            sa = A[2 * k];
-            ea = A[2 * k + 1];
+            const int2 ca = cand<ROWX>(x, A, na_raw, k);
+            sa = ca.x;
+            ea = ca.y;
+        }
+        if (k < na && sa < ea) {
             int lo = 0, hi = nb;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (B[2 * mid + 1] > sa) hi = mid; else lo = mid + 1;
+                if (cand<ROWX>(x, B, nb_raw, mid).y > sa) hi = mid; else lo = mid + 1;
             }
             j0 = lo;
-            for (int j = j0; j < nb && B[2 * j] < ea; j++) c++;
+            for (int j = j0; j < nb; j++) {
+                const int2 cb = cand<ROWX>(x, B, nb_raw, j);
+                if (cb.x >= ea) break;
+                span++;
+                c += live(cb);
+            }
         }
         const int inc = group_incl_scan(c);
         long long idx = carry + inc - c;
-        if (k < na) {
-            for (int j = j0; j < nb && B[2 * j] < ea; j++) {
-                if (idx < cap_row) {
-                    o[2 * idx] = max(sa, B[2 * j]);
-                    o[2 * idx + 1] = min(ea, B[2 * j + 1]);
-                }
-                idx++;
+        for (int j = j0; j < j0 + span; j++) {
+            const int2 cb = cand<ROWX>(x, B, nb_raw, j);
+            if (!live(cb)) continue;
+            if (idx < cap_row) {
+                o[2 * idx] = max(sa, cb.x);
+                o[2 * idx + 1] = min(ea, cb.y);
             }
+            idx++;
         }
         carry += group_last(inc);
     }
@@ -442,6 +479,7 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+template <bool ROWX>
 __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], int na, const int2 *sB, int nb,
                                                       int2 *__restrict__ o, int cap)
 {
@@ -452,33 +490,59 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
         if (m * kGroup >= na) break;
         const int k = m * kGroup + gl;
         const int sa = a[m].x, ea = a[m].y;
-        // j0 = the first run of B that ends after sa starts (ends ascend)
-        int lo = 0, hi = nb;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
-        }
-        const int j0 = lo;
-        int c = 0;
-        if (k < na) {
+        int c = 0, span = 0, j0 = 0;
+        if (k < na && sa < ea) {
+            // j0 = the first candidate of B that ends after sa (ends ascend)
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
+            }
+            j0 = lo;
             // most runs overlap at most two runs of the other row
             const int2 b0 = sB[min(j0, nb - 1)], b1 = sB[min(j0 + 1, nb - 1)];
             const bool h0 = j0 < nb && b0.x < ea;
             const bool h1 = h0 && j0 + 1 < nb && b1.x < ea;
-            c = (int)h0 + (int)h1;
+            span = (int)h0 + (int)h1;
+            c = ROWX ? (int)(h0 && live(b0)) + (int)(h1 && live(b1)) : span;
             if (h1)
-                for (int j = j0 + 2; j < nb && sB[j].x < ea; j++) c++;
+                for (int j = j0 + 2; j < nb && sB[j].x < ea; j++) {
+                    span++;
+                    c += ROWX ? (int)live(sB[j]) : 1;
+                }
         }
         const int inc = group_incl_scan(c);
-        const int idx = carry + inc - c;
-        const int lim = min(c, cap - idx);          // never past the slot row
-        for (int q = 0; q < lim; q++) {
+        int idx = carry + inc - c;
+        for (int q = 0; q < span; q++) {
             const int2 b = sB[j0 + q];
-            o[idx + q] = make_int2(max(sa, b.x), min(ea, b.y));
+            if (ROWX && !live(b)) continue;
+            if (idx < cap) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
+            idx++;
         }
         carry += group_last(inc);
     }
     return carry;
+}
+
+// Candidates of a row held in registers (lane k holds raw runs k + 16 m):
+// in place, the gaps of the complement taking the end of the run before
+// from the lane before (or lane 15 of the block before).
+__device__ __forceinline__ void shrink_regs(const RowX &x, int2 (&v)[kARegs], int n)
+{
+    const int gl = glane();
+    int prev_end = 0;
+#pragma unroll
+    for (int m = 0; m < kARegs; m++) {
+        const int k = m * kGroup + gl;
+        if (x.comp) {
+            const int pe = __builtin_amdgcn_update_dpp(prev_end, v[m].y, 0x111, 0xf, 0xf, false);
+            const int lastend = group_last(v[m].y);
+            v[m] = shrink(x, k == 0 ? 0 : pe, k == n ? x.W : v[m].x);
+            prev_end = lastend;
+        } else {
+            v[m] = shrink(x, v[m].x, v[m].y);
+        }
+    }
 }
 
 // One doubling step between lines (sections "Between Line Boolean
@@ -487,8 +551,9 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
 // stored row x - off if that lies in [0, real), and otherwise a full row
 // [0, W) (outside the image erosion sees 1s).  NA rows per page come in,
 // NA - K go out.  One group of lanes per output row.
+template <bool ROWX>
 __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, int P,
-                                                      int W, int *__restrict__ out_cnt,
+                                                      int W, RowX x, int *__restrict__ out_cnt,
                                                       int *__restrict__ out_runs, long long cap_row,
                                                       unsigned long long *trace)
 {
@@ -512,23 +577,41 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
         }
         return;
     }
+    const int extra = (ROWX && x.comp) ? 1 : 0;      // a row of n runs has n + extra candidates
     if (!va || !vb) {                       // full row AND x = x
         long long base;
         int n;
         row_span(in, (long long)page * real + (va ? ia : ib), base, n);
-        n = (int)min((long long)n, cap_row);
         const int *src = in.runs + 2 * base;
-        for (int k = gl; k < n; k += kGroup) {
-            o[2 * k] = src[2 * k];
-            o[2 * k + 1] = src[2 * k + 1];
+        int cnt = 0;
+        if (!ROWX) {
+            n = (int)min((long long)n, cap_row);
+            for (int k = gl; k < n; k += kGroup) {
+                o[2 * k] = src[2 * k];
+                o[2 * k + 1] = src[2 * k + 1];
+            }
+            cnt = n;
+        } else {
+            // the live candidates, compacted by ballot
+            const int nc = n + extra;
+            for (int k0 = 0; k0 < nc; k0 += kGroup) {
+                const int k = k0 + gl;
+                const int2 c = k < nc ? cand<true>(x, src, n, k) : make_int2(0, 0);
+                const bool keep = k < nc && live(c);
+                const unsigned gm = group_ballot(keep);
+                const int idx = cnt + __popc(gm & ((1u << gl) - 1));
+                if (keep && idx < cap_row) ((int2 *)o)[idx] = c;
+                cnt += __popc(gm);
+            }
+            cnt = (int)min((long long)cnt, cap_row);
         }
         if (gl == 0) {
-            out_cnt[t] = n;
+            out_cnt[t] = cnt;
             // input runs: the A row (if stored); the B row only where it is
             // never an A row (r + K >= NB)
             if (trace)
                 trace_add(trace, (unsigned long long)((va ? n : 0) + (vb && r + K >= NB ? n : 0)),
-                          (unsigned long long)n);
+                          (unsigned long long)cnt);
         }
         return;
     }
@@ -539,14 +622,15 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     const int *A = in.runs + 2 * ba;
     const int *B = in.runs + 2 * bb;
     // the intersection is symmetric: the shorter row goes to registers and
-    // its runs to the lanes, the longer one is searched
+    // its candidates to the lanes, the longer one is searched
     const bool swap = nb < na;
     const int *S = swap ? B : A, *L = swap ? A : B;
-    const int ns = min(na, nb), nl = max(na, nb);
+    const int ns = min(na, nb), nl = max(na, nb);        // runs stored
+    const int cs = ns + extra, cl = nl + extra;           // candidates
     int cnt = 0;
-    if (ns == 0) {
+    if (cs == 0) {
         cnt = 0;
-    } else if (nl <= kStageRuns) {
+    } else if (cl <= kStageRuns) {
         const int2 *S2 = (const int2 *)S, *L2 = (const int2 *)L;
         int2 a[kARegs], b[kARegs];
 #pragma unroll
@@ -555,14 +639,18 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
             a[m] = k < ns ? S2[k] : make_int2(0, 0);
             b[m] = k < nl ? L2[k] : make_int2(0, 0);
         }
+        if (ROWX) {
+            shrink_regs(x, a, ns);
+            shrink_regs(x, b, nl);
+        }
         int2 *sB = stage[threadIdx.x >> 4];
 #pragma unroll
         for (int m = 0; m < kARegs; m++)
-            if (m * kGroup + gl < nl) sB[m * kGroup + gl] = b[m];
+            if (m * kGroup + gl < cl) sB[m * kGroup + gl] = b[m];
         wave_lds_sync();
-        cnt = group_intersect_staged(a, ns, sB, nl, (int2 *)o, (int)cap_row);
+        cnt = group_intersect_staged<ROWX>(a, cs, sB, cl, (int2 *)o, (int)cap_row);
     } else {
-        cnt = group_intersect(S, ns, L, nl, o, cap_row);
+        cnt = group_intersect<ROWX>(x, S, ns, cs, L, nl, cl, o, cap_row);
     }
     if (gl == 0) {
         out_cnt[t] = (int)min((long long)cnt, cap_row);
@@ -782,33 +870,45 @@ static RowsIn slot_rows(const RleWs &L, int i)
 }
 
 // Erosion of P pages (or of their complements, comp_in) by the rectangle
-// (w, h, cx, cy): the within-line pass into slot buffer `to`, then the
-// doubling steps between lines, alternating buffers.  Returns the buffer
-// that holds the P*H result rows.
+// (w, h, cx, cy) into slot buffer `to` and the other one, alternating.  With
+// h = 1 it is the within-line pass alone.  Otherwise the first doubling step
+// between lines reads `in` itself and applies the within-line pass to each
+// row as it reads it; the other steps follow.  Returns the buffer that holds
+// the P*H result rows.  `in` may be the other slot buffer, never `to`.
 static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w, int h, int cx, int cy,
                        const RleWs &L, int to, hipStream_t s, hipError_t *err)
 {
     const int R = P * H;
     unsigned long long *tr = trace_counters();
-    trace_before(MORPH_K_ROW_ERODE, s);
-    hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
-                       cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row,
-                       trace_block(tr, MORPH_K_ROW_ERODE));
-    trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
-    int cur = to;
+    if (h == 1) {
+        trace_before(MORPH_K_ROW_ERODE, s);
+        hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
+                           cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row,
+                           trace_block(tr, MORPH_K_ROW_ERODE));
+        trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
+        *err = hipGetLastError();
+        return to;
+    }
     // rows of the extended page: 0 .. H+h-2, row x being image row x - cy
     int off = cy, real = H, NA = H + h - 1;
     int m = 1;
     int offs[40], n = 0;
     while (2 * m <= h) { offs[n++] = m; m *= 2; }
     if (h > m) offs[n++] = h - m;
+    const RowX x{cx, w - 1 - cx, comp_in, W};
+    int cur = -1;                           // -1: the input rows
     for (int k = 0; k < n; k++) {
         const int K = offs[k], NB = NA - K;
-        const int nxt = 1 - cur;
+        const int nxt = cur < 0 ? to : 1 - cur;
+        const dim3 grid(blocks_for((long long)P * NB, kGroupsPerBlock));
         trace_before(MORPH_K_COL_AND, s);
-        hipLaunchKernelGGL(col_and_kernel, dim3(blocks_for((long long)P * NB, kGroupsPerBlock)), dim3(256), 0, s,
-                           slot_rows(L, cur), off, real, NA, K, P, W, L.cnt[nxt], L.runs[nxt],
-                           (long long)L.cap_row, trace_block(tr, MORPH_K_COL_AND));
+        if (cur < 0)
+            hipLaunchKernelGGL(col_and_kernel<true>, grid, dim3(256), 0, s, in, off, real, NA, K, P, W, x,
+                               L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, trace_block(tr, MORPH_K_COL_AND));
+        else
+            hipLaunchKernelGGL(col_and_kernel<false>, grid, dim3(256), 0, s, slot_rows(L, cur), off, real, NA, K,
+                               P, W, x, L.cnt[nxt], L.runs[nxt], (long long)L.cap_row,
+                               trace_block(tr, MORPH_K_COL_AND));
         trace_after(MORPH_K_COL_AND, s, 4.0 * P * ((double)real + NB));
         cur = nxt;
         off = 0;

@@ -189,9 +189,14 @@ def test_trace_counts_launches_and_bytes():
     assert res["rect_kernel"]["ms"] > 0
     n = int(oracle.rle_encode(img)[0][-1])
     assert res["pack_to_rle_kernel"]["bytes"] == 8 * 8 * H + 4 * (H + 1) + 8 * n
-    assert res["col_and_kernel"]["launches"] == 3          # offsets 1, 2, then 1
-    assert res["row_erode_kernel"]["launches"] == 1
+    # offsets 1, 2, then 1; the within-line pass runs inside the first of them
+    assert res["col_and_kernel"]["launches"] == 3
+    assert res.get("row_erode_kernel", {"launches": 0})["launches"] == 0
     assert res["pack_rows_kernel"]["launches"] == 1
+    with M.Trace() as tr:
+        M.rect_rle("erode", r, (7, 1, 3, 0))                 # one row: the within-line pass alone
+    assert tr.result["row_erode_kernel"]["launches"] == 1
+    assert tr.result.get("col_and_kernel", {"launches": 0})["launches"] == 0
 
 
 @pytest.mark.parametrize("op", pagegen.OPS)

@@ -51,7 +51,11 @@ def served(reqs, arrivals, budget=64 << 30):
 def test_mix_equals_alone_equals_plain_equals_oracle():
     from paper_0712_0121_amd.serve import PlainRunner
     reqs = make_requests(20)
-    arrivals = np.cumsum(np.random.default_rng(1).exponential(0.002, len(reqs)))
+    # staggered arrivals (some while others run), and every third request
+    # arriving together with the one before it, so launches must be shared
+    gaps = np.random.default_rng(1).exponential(0.0005, len(reqs))
+    gaps[2::3] = 0.0
+    arrivals = np.cumsum(gaps)
     s = served(reqs, arrivals)
     assert len(s.completed) == len(reqs)
     assert s.launches < 4 * len(reqs)           # operations shared launches
