@@ -169,7 +169,9 @@ int morph_close_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_s
  */
 int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src,
                       void *ws, size_t ws_bytes, morph_stream_t stream);
-/* Run-length image -> packed bitmap (pad bits 0).  src must be canonical. */
+/* Run-length image -> packed bitmap (pad bits 0).  src must be canonical;
+ * offsets in row_ptr are clamped to src->capacity.  MORPH_E_UNSUPPORTED when
+ * rows * words per row reaches 2^32. */
 int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_stream_t stream);
 
 /* ---- sizes and checks --------------------------------------------------- */
