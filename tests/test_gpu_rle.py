@@ -228,3 +228,31 @@ def test_letter_batch_as_timed(op):
         for i in range(D, B):
             np.testing.assert_array_equal(counts[i], counts[i % D])
         del pk, back, r_out
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+@pytest.mark.parametrize("se", [(3, 5, 1, 2), (1, 9, 0, 4), (6, 4, 5, 0)])
+def test_rle_long_rows(op, se):
+    """Rows of several hundred runs (more than a group keeps in registers or
+    LDS), so the within-line pass, every column step (the first one with
+    the within-line erosion applied as rows are read) and the final packing
+    take their global-memory paths; one page mixes long rows with short."""
+    W, H = 1500, 60
+    r = np.random.default_rng(11)
+    img = (r.random((H, W)) < 0.5).astype(np.uint8)
+    img[40:45] = 0                                 # short rows beside the long ones
+    img[40:45, 100:400] = 1
+    img[42, 900:1000] = 1
+    n = np.diff(oracle.rle_encode(img)[0])
+    assert n.max() > 300 and n.min() < 128
+    assert_rle_equal(rle_op(op, img, se), oracle.apply(op, img, se), "%s %s" % (op, se))
+
+
+def test_rle_alternating_rows_all_ops():
+    """The worst case for run counts, ceil(W/2) runs in every row."""
+    W, H = 700, 24
+    img = np.tile((np.arange(W) % 2 == 0).astype(np.uint8), (H, 1))
+    img[::3] ^= 1
+    for op in pagegen.OPS:
+        for se in [(2, 2, 0, 1), (1, 5, 0, 2), (3, 1, 1, 0)]:
+            assert_rle_equal(rle_op(op, img, se), oracle.apply(op, img, se), "%s %s" % (op, se))
