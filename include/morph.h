@@ -254,8 +254,9 @@ enum {
     MORPH_K_RECT_BATCH = 1,    /* persistent batched packed kernel */
     MORPH_K_PACK_TO_RLE = 2,   /* bitmap -> runs (count and emit launches) */
     MORPH_K_RLE_TO_PACK = 3,   /* runs -> bitmap */
-    MORPH_K_ROW_ERODE = 4,     /* within-line pass on runs */
-    MORPH_K_COL_AND = 5,       /* between-line doubling step on runs */
+    MORPH_K_ROW_ERODE = 4,     /* within-line pass on runs (elements one row tall) */
+    MORPH_K_COL_AND = 5,       /* between-line doubling step on runs; the first step of a
+                                  chain also applies the within-line pass to the rows it reads */
     MORPH_K_PACK_ROWS = 6,     /* final packing of run rows into CSR */
     MORPH_K_COUNT = 7
 };
