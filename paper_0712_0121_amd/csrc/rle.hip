@@ -491,6 +491,8 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
         const int k = m * kGroup + gl;
         const int sa = a[m].x, ea = a[m].y;
         int c = 0, span = 0, j0 = 0;
+        int2 b0 = make_int2(0, 0), b1 = make_int2(0, 0);
+        bool e0 = false, e1 = false;        // b0, b1 overlap and are emitted
         if (k < na && sa < ea) {
             // j0 = the first candidate of B that ends after sa (ends ascend)
             int lo = 0, hi = nb;
@@ -499,21 +501,36 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
                 if (sB[mid].y > sa) hi = mid; else lo = mid + 1;
             }
             j0 = lo;
-            // most runs overlap at most two runs of the other row
-            const int2 b0 = sB[min(j0, nb - 1)], b1 = sB[min(j0 + 1, nb - 1)];
+            // most runs overlap at most two runs of the other row: those two
+            // stay in registers for the emission
+            b0 = sB[min(j0, nb - 1)];
+            b1 = sB[min(j0 + 1, nb - 1)];
             const bool h0 = j0 < nb && b0.x < ea;
             const bool h1 = h0 && j0 + 1 < nb && b1.x < ea;
+            e0 = h0 && (!ROWX || live(b0));
+            e1 = h1 && (!ROWX || live(b1));
             span = (int)h0 + (int)h1;
-            c = ROWX ? (int)(h0 && live(b0)) + (int)(h1 && live(b1)) : span;
-            if (h1)
+            c = (int)e0 + (int)e1;
+            if (h1) {
+#pragma unroll 1
                 for (int j = j0 + 2; j < nb && sB[j].x < ea; j++) {
                     span++;
                     c += ROWX ? (int)live(sB[j]) : 1;
                 }
+            }
         }
         const int inc = group_incl_scan(c);
         int idx = carry + inc - c;
-        for (int q = 0; q < span; q++) {
+        if (e0) {
+            if (idx < cap) o[idx] = make_int2(max(sa, b0.x), min(ea, b0.y));
+            idx++;
+        }
+        if (e1) {
+            if (idx < cap) o[idx] = make_int2(max(sa, b1.x), min(ea, b1.y));
+            idx++;
+        }
+#pragma unroll 1
+        for (int q = 2; q < span; q++) {
             const int2 b = sB[j0 + q];
             if (ROWX && !live(b)) continue;
             if (idx < cap) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
