@@ -33,7 +33,7 @@ __all__ = [
     "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
-    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes",
+    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes", "page_desc",
     "morph_batch_launch", "Trace",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack",
 ]
@@ -389,11 +389,22 @@ def morph_batch_workspace_bytes(items) -> int:
     return int(_lib.morph_batch_workspace_bytes(arr, n))
 
 
+def page_desc(dst: "Bitmap", src: "Bitmap", op, s, tile_rows=0, strip_words=0) -> morph_page_desc_t:
+    """One batch descriptor, built once and reusable while dst and src live."""
+    return morph_page_desc_t(dst.struct(), src.struct(), OPS.index(op) if isinstance(op, str) else op,
+                             _se(s), int(tile_rows), int(strip_words))
+
+
 def morph_batch_launch(items, ws, staging=None, stream=None):
     """One persistent launch over the items (see morph_batch_launch in
     include/morph.h); ws: device uint8 tensor; staging: pinned host uint8
-    tensor or None."""
-    arr, n = _descs(items)
+    tensor or None.  items: (dst, src, op, se[, tile_rows, strip_words])
+    tuples, or prebuilt page_desc() descriptors."""
+    items = list(items)
+    if items and isinstance(items[0], morph_page_desc_t):
+        arr, n = (morph_page_desc_t * len(items))(*items), len(items)
+    else:
+        arr, n = _descs(items)
     p, nb = _ws(ws)
     if staging is not None:
         sp, sn = ctypes.c_void_p(staging.data_ptr()), staging.numel()

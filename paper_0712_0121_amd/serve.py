@@ -209,7 +209,8 @@ class GpuExecutor:
     # every launch a later download waits for
     downloads_in_order = True
 
-    def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4, direct_max=2):
+    def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4, direct_max=2,
+                 recycle_outputs=False):
         import torch
         import paper_0712_0121_amd as M
         self.M, self.torch = M, torch
@@ -222,6 +223,11 @@ class GpuExecutor:
         self.staging_ev = [None] * staging_slots
         self.slot = 0
         self.direct_max = direct_max
+        # with recycle_outputs the pinned result buffers go back to a pool per
+        # page shape on release: only for a server that does not keep results
+        # (Server(keep_results=False)), since a kept result is a view of one
+        self.recycle = recycle_outputs
+        self.out_pool = collections.defaultdict(list)
 
     def footprint(self, r: Request) -> int:
         return 2 * r.H * ((r.W + 63) // 64) * 8
@@ -246,7 +252,11 @@ class GpuExecutor:
             if up is not self.compute:
                 ev = torch.cuda.Event()
                 ev.record(up)
-        r.state = {"cur": a, "nxt": b, "up": ev, "host": host}
+        # the chain's batch descriptors, built once: operation k reads the
+        # buffer written by operation k-1
+        bufs = (a, b)
+        descs = [M.page_desc(bufs[(k + 1) % 2], bufs[k % 2], op, se) for k, (op, se) in enumerate(r.chain)]
+        r.state = {"cur": a, "nxt": b, "up": ev, "host": host, "descs": descs}
 
     def launch(self, reqs):
         torch, M = self.torch, self.M
@@ -256,12 +266,12 @@ class GpuExecutor:
             if st.get("up") is not None:
                 self.compute.wait_event(st["up"])
                 st["up"] = None
-            op, se = r.chain[r.pos]
-            items.append((st["nxt"], st["cur"], op, se))
+            items.append(st["descs"][r.pos])
         if len(items) <= self.direct_max:
             with torch.cuda.stream(self.compute):
-                for dst, src, op, se in items:
-                    M.PACKED[op](dst, src, se, self.ws)
+                for r in reqs:
+                    op, se = r.chain[r.pos]
+                    M.PACKED[op](r.state["nxt"], r.state["cur"], se, self.ws)
                 ev = torch.cuda.Event()
                 ev.record(self.compute)
             for r in reqs:
@@ -292,7 +302,9 @@ class GpuExecutor:
     def begin_download(self, r: Request):
         torch = self.torch
         st = r.state
-        out = torch.empty((r.H, st["cur"].stride), dtype=torch.int64, pin_memory=True)
+        shape = (r.H, st["cur"].stride)
+        pool = self.out_pool[shape] if self.recycle else None
+        out = pool.pop() if pool else torch.empty(shape, dtype=torch.int64, pin_memory=True)
         down = self.compute if r.alone else self.down
         with torch.cuda.stream(down):
             if down is not self.compute:
@@ -309,6 +321,9 @@ class GpuExecutor:
         return r.state["out"].numpy().view(np.uint64)
 
     def release(self, r: Request):
+        out, down = r.state.get("out"), r.state.get("down")
+        if self.recycle and out is not None and down is not None and down.query():
+            self.out_pool[tuple(out.shape)].append(out)
         r.state = {}
 
 
