@@ -419,6 +419,21 @@ __device__ __forceinline__ int2 cand(const RowX &x, const int *R, int n, int k)
     return shrink(x, R[2 * k], R[2 * k + 1]);
 }
 
+// Whether a row's live candidates cover pixel 0 and pixel W-1.  Only the
+// first candidate can start at 0 and only the last can end at W.
+template <bool ROWX>
+__device__ __forceinline__ void row_ends(const RowX &x, const int *R, int n, int W, bool &has0, bool &hasW)
+{
+    const int nc = n + ((ROWX && x.comp) ? 1 : 0);
+    if (nc == 0) {
+        has0 = hasW = false;
+        return;
+    }
+    const int2 f = cand<ROWX>(x, R, n, 0), l = cand<ROWX>(x, R, n, nc - 1);
+    has0 = live(f) && f.x == 0;
+    hasW = live(l) && l.y == W;
+}
+
 // Intersection of the rows A (na candidates) and B (nb candidates) into o,
 // by the lanes of one group: lane k takes candidates k, k+16, ... of A,
 // finds the first candidate of B that ends after it starts, and emits every
@@ -572,8 +587,11 @@ template <bool ROWX>
 __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, int P,
                                                       int W, RowX x, int *__restrict__ out_cnt,
                                                       int *__restrict__ out_runs, long long cap_row,
-                                                      unsigned long long *trace)
+                                                      int *__restrict__ gap_cnt, unsigned long long *trace)
 {
+    // gap_cnt (the last step of a chain whose result is complemented): also
+    // the run count of each output row's complement, which is its run count
+    // plus one, less one for each border pixel the row covers
     __shared__ int2 stage[kGroupsPerBlock][kStageRuns];
     const int NB = NA - K;
     const long long t = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
@@ -590,6 +608,7 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
             o[0] = 0;
             o[1] = W;
             out_cnt[t] = 1;
+            if (gap_cnt) gap_cnt[t] = 0;
             if (trace) trace_add(trace, 0, 1ull);
         }
         return;
@@ -624,6 +643,11 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
         }
         if (gl == 0) {
             out_cnt[t] = cnt;
+            if (gap_cnt) {
+                bool h0, hW;
+                row_ends<ROWX>(x, src, n, W, h0, hW);
+                gap_cnt[t] = cnt + 1 - (int)h0 - (int)hW;
+            }
             // input runs: the A row (if stored); the B row only where it is
             // never an A row (r + K >= NB)
             if (trace)
@@ -671,6 +695,12 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     }
     if (gl == 0) {
         out_cnt[t] = (int)min((long long)cnt, cap_row);
+        if (gap_cnt) {
+            bool a0, aW, b0, bW;
+            row_ends<ROWX>(x, A, na, W, a0, aW);
+            row_ends<ROWX>(x, B, nb, W, b0, bW);
+            gap_cnt[t] = (int)min((long long)cnt, cap_row) + 1 - (int)(a0 && b0) - (int)(aW && bW);
+        }
         if (trace) trace_add(trace, (unsigned long long)(na + (r + K >= NB ? nb : 0)), (unsigned long long)cnt);
     }
 }
@@ -893,8 +923,10 @@ static RowsIn slot_rows(const RleWs &L, int i)
 // row as it reads it; the other steps follow.  Returns the buffer that holds
 // the P*H result rows.  `in` may be the other slot buffer, never `to`.
 static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w, int h, int cx, int cy,
-                       const RleWs &L, int to, hipStream_t s, hipError_t *err)
+                       const RleWs &L, int to, hipStream_t s, hipError_t *err, int *gap_out = nullptr,
+                       bool *gaps_done = nullptr)
 {
+    if (gaps_done) *gaps_done = false;
     const int R = P * H;
     unsigned long long *tr = trace_counters();
     if (h == 1) {
@@ -918,14 +950,17 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
         const int K = offs[k], NB = NA - K;
         const int nxt = cur < 0 ? to : 1 - cur;
         const dim3 grid(blocks_for((long long)P * NB, kGroupsPerBlock));
+        int *gaps = (k == n - 1) ? gap_out : nullptr;   // the last step counts the complement's runs
         trace_before(MORPH_K_COL_AND, s);
         if (cur < 0)
             hipLaunchKernelGGL(col_and_kernel<true>, grid, dim3(256), 0, s, in, off, real, NA, K, P, W, x,
-                               L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, trace_block(tr, MORPH_K_COL_AND));
+                               L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, gaps,
+                               trace_block(tr, MORPH_K_COL_AND));
         else
             hipLaunchKernelGGL(col_and_kernel<false>, grid, dim3(256), 0, s, slot_rows(L, cur), off, real, NA, K,
-                               P, W, x, L.cnt[nxt], L.runs[nxt], (long long)L.cap_row,
+                               P, W, x, L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, gaps,
                                trace_block(tr, MORPH_K_COL_AND));
+        if (gaps && gaps_done) *gaps_done = true;
         trace_after(MORPH_K_COL_AND, s, 4.0 * P * ((double)real + NB));
         cur = nxt;
         off = 0;
@@ -937,16 +972,17 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
 }
 
 // Packs the P*H slot rows of buffer b (complemented when comp) into dst.
-static hipError_t finish(const RleWs &L, int b, int comp, const morph_rle_t &dst, int W, hipStream_t s)
+// With gaps_done the complement's counts are already in L.fcount.
+static hipError_t finish(const RleWs &L, int b, int comp, const morph_rle_t &dst, int W, hipStream_t s,
+                         bool gaps_done)
 {
     const int R = dst.height * dst.npages;
-    const int *counts = L.cnt[b];
+    const int *counts = comp ? L.fcount : L.cnt[b];
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_PACK_ROWS, s);
-    if (comp) {
+    if (comp && !gaps_done) {
         hipLaunchKernelGGL(gap_count_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, s, slot_rows(L, b), R, W,
                            L.fcount);
-        counts = L.fcount;
     }
     hipError_t e = exclusive_scan(counts, R, dst.row_ptr, L.tmp, s);
     if (e != hipSuccess) return e;
@@ -971,24 +1007,25 @@ hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, m
     const int w = se.w, h = se.h, cx = se.cx, cy = se.cy;
     const int rx = w - 1 - cx, ry = h - 1 - cy;
     hipError_t e = hipSuccess;
+    bool g = false;                 // the complement's counts came with the last step
     int b;
     switch (op) {
     case MORPH_ERODE:
         b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
-        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s);
+        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s, false);
     case MORPH_DILATE:
-        b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e);
-        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s);
+        b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e, L.fcount, &g);
+        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s, g);
     case MORPH_OPEN:
         b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
         if (e != hipSuccess) return e;
-        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, rx, ry, L, 1 - b, s, &e);
-        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s);
+        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, rx, ry, L, 1 - b, s, &e, L.fcount, &g);
+        return e != hipSuccess ? e : finish(L, b, 1, dst, W, s, g);
     case MORPH_CLOSE:
         b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e);
         if (e != hipSuccess) return e;
         b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, cx, cy, L, 1 - b, s, &e);
-        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s);
+        return e != hipSuccess ? e : finish(L, b, 0, dst, W, s, false);
     }
     return hipErrorInvalidValue;
 }
