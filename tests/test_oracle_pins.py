@@ -458,3 +458,67 @@ def test_generators_deterministic_and_in_band():
     assert words.shape == (3300, 40)
     np.testing.assert_array_equal(oracle.unpack(words, 2550), p.img)
     np.testing.assert_array_equal(oracle.pack(p.img, 40), words)
+
+
+# ------------------------------------------------------------ transposition
+from oracle import transpose as otr  # noqa: E402
+
+
+def test_transpose_hand_example():
+    """A 3 x 5 image and its 5 x 3 transpose, written out by hand."""
+    rows = ["11001",
+            "01101",
+            "00111"]
+    img = np.array([[int(c) for c in r] for r in rows], dtype=np.uint8)
+    want_rows = ["100",
+                 "110",
+                 "011",
+                 "001",
+                 "111"]
+    want = np.array([[int(c) for c in r] for r in want_rows], dtype=np.uint8)
+    rp, runs = oracle.rle_encode(img)
+    trp, truns = otr.rle_transpose(rp, runs, 5, 3)
+    np.testing.assert_array_equal(oracle.rle_decode(trp, truns, 3, 5), want)
+    # the runs of column 4 (row 4 of the transpose): one run over all 3 rows
+    assert [tuple(r) for r in truns[trp[4]:trp[5]]] == [(0, 3)]
+    assert [tuple(r) for r in truns[trp[1]:trp[2]]] == [(0, 2)]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_simple_transpose_matches_decode_recode(seed):
+    r = np.random.default_rng(seed)
+    H, W = int(r.integers(1, 40)), int(r.integers(1, 70))
+    img = rnd_img(100 + seed, H, W, float(r.choice([0.05, 0.5, 0.95])))
+    rp, runs = oracle.rle_encode(img)
+    want = otr.rle_transpose(rp, runs, W, H)
+    got = otr.from_lines(otr.transpose_lines(otr.to_lines(rp, runs), W))
+    np.testing.assert_array_equal(got[0], want[0])
+    np.testing.assert_array_equal(got[1].reshape(-1, 2), want[1].reshape(-1, 2))
+
+
+def test_transpose_twice_is_identity_and_degenerate_shapes():
+    for H, W, p in [(1, 1, 1.0), (1, 1, 0.0), (1, 67, 0.5), (67, 1, 0.5), (64, 64, 0.5),
+                    (65, 130, 0.3), (5, 5, 0.0), (5, 5, 1.0)]:
+        img = rnd_img(H * 1000 + W, H, W, p)
+        rp, runs = oracle.rle_encode(img)
+        trp, truns = otr.rle_transpose(rp, runs, W, H)
+        np.testing.assert_array_equal(oracle.rle_decode(trp, truns, H, W), img.T)
+        brp, bruns = otr.rle_transpose(trp, truns, H, W)
+        np.testing.assert_array_equal(brp, rp)
+        np.testing.assert_array_equal(bruns.reshape(-1, 2), runs.reshape(-1, 2))
+
+
+@pytest.mark.parametrize("op", oracle.OPS)
+def test_transpose_composition_matches_oracle(op):
+    """Within-line operations plus transposition give the rectangle
+    operation (separability), including the borders."""
+    r = np.random.default_rng(7)
+    for k in range(12):
+        H, W = int(r.integers(1, 30)), int(r.integers(1, 50))
+        img = rnd_img(200 + k, H, W, float(r.choice([0.3, 0.6, 0.85])))
+        w, h = int(r.integers(1, 9)), int(r.integers(1, 9))
+        se = (w, h, int(r.integers(0, w)), int(r.integers(0, h)))
+        rp, runs = oracle.rle_encode(img)
+        grp, gruns = otr.rlet_apply(op, rp, runs, W, se)
+        np.testing.assert_array_equal(oracle.rle_decode(grp, gruns, W, H), oracle.apply(op, img, se),
+                                      err_msg="%s %s %dx%d" % (op, se, H, W))
