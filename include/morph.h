@@ -174,6 +174,42 @@ int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src,
  * rows * words per row reaches 2^32. */
 int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_stream_t stream);
 
+/* ---- transposition (section "Efficient Transpose") ---------------------- */
+/*
+ * Transpose of every page: dst row x holds column x of src.  dst->width must
+ * equal src->height, dst->height src->width, and npages must agree
+ * (MORPH_E_SHAPE otherwise).  Packed: one read of src and one write of dst,
+ * pad bits of dst written 0.
+ */
+int morph_transpose_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_stream_t stream);
+/*
+ * Run-length transpose: dst row x holds the runs of column x of src (the
+ * runs are decoded 64 x 64 pixels at a time straight into the transposed
+ * bitmap, which is then re-encoded).  dst->capacity must be at least
+ * morph_rle_max_runs(src->height, src->width * npages) (MORPH_E_CAPACITY);
+ * ws: 256-byte aligned, at least morph_transpose_rle_workspace_bytes(src
+ * width, src height, npages) bytes.
+ */
+int morph_transpose_rle(const morph_rle_t *dst, const morph_rle_t *src, void *ws, size_t ws_bytes,
+                        morph_stream_t stream);
+size_t morph_transpose_rle_workspace_bytes(int32_t width, int32_t height, int32_t npages);
+/*
+ * The rectangle operations on run-length images by within-line operations
+ * and transposition (section "2D Morphological Operators for Rectangular
+ * Masks", second strategy; the erode2d composition of section "Run Length
+ * Image Coding"): the within-line operation along the rows, transpose, the
+ * within-line operation along the former columns, transpose back.  Same
+ * result as morph_<op>_rect_rle.  op: MORPH_ERODE .. MORPH_CLOSE.
+ * dst->capacity as for morph_<op>_rect_rle; ws: 256-byte aligned, at least
+ * morph_rlet_workspace_bytes(op, width, height, npages, se) bytes (it holds
+ * a run buffer of the worst-case size of the transposed image, about
+ * 4 bytes per pixel).  MORPH_E_UNSUPPORTED when that worst case reaches
+ * 2^31 runs.
+ */
+int morph_rect_rlet(int op, const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                    size_t ws_bytes, morph_stream_t stream);
+size_t morph_rlet_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se);
+
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
  * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
@@ -258,7 +294,10 @@ enum {
     MORPH_K_COL_AND = 5,       /* between-line doubling step on runs; the first step of a
                                   chain also applies the within-line pass to the rows it reads */
     MORPH_K_PACK_ROWS = 6,     /* final packing of run rows into CSR */
-    MORPH_K_COUNT = 7
+    MORPH_K_TRANSPOSE = 7,     /* packed bitmap -> its transpose */
+    MORPH_K_DECODE_T = 8,      /* runs -> transposed packed bitmap, with a within-line
+                                  operation applied to the runs as they are read */
+    MORPH_K_COUNT = 9
 };
 typedef struct {
     int64_t launches;

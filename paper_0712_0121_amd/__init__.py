@@ -35,7 +35,9 @@ __all__ = [
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
     "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes", "page_desc",
     "morph_batch_launch", "Trace",
-    "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack",
+    "morph_transpose_packed", "morph_transpose_rle", "morph_transpose_rle_workspace_bytes",
+    "morph_rect_rlet", "morph_rlet_workspace_bytes",
+    "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack", "transpose_packed", "transpose_rle", "rect_rlet",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmorph.so")
@@ -69,7 +71,7 @@ class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 7
+MORPH_K_COUNT = 9
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -104,6 +106,11 @@ def _load():
         "morph_trace_begin": (ctypes.c_int, [P, SZ, P]),
         "morph_trace_end": (ctypes.c_int, [ctypes.POINTER(morph_kernel_trace_t), P]),
         "morph_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
+        "morph_transpose_packed": (ctypes.c_int, [BM, BM, P]),
+        "morph_transpose_rle": (ctypes.c_int, [RL, RL, P, SZ, P]),
+        "morph_transpose_rle_workspace_bytes": (SZ, [I32, I32, I32]),
+        "morph_rect_rlet": (ctypes.c_int, [ctypes.c_int, RL, RL, SE, P, SZ, P]),
+        "morph_rlet_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -331,6 +338,36 @@ def morph_rle_validate(r: RLE, stream=None) -> int:
     return int(_lib.morph_rle_validate(ctypes.byref(s), _stream(stream)))
 
 
+def morph_transpose_packed(dst: Bitmap, src: Bitmap, stream=None):
+    d, r = dst.struct(), src.struct()
+    _check(_lib.morph_transpose_packed(ctypes.byref(d), ctypes.byref(r), _stream(stream)),
+           "morph_transpose_packed")
+
+
+def morph_transpose_rle_workspace_bytes(width, height, npages=1) -> int:
+    return int(_lib.morph_transpose_rle_workspace_bytes(int(width), int(height), int(npages)))
+
+
+def morph_transpose_rle(dst: RLE, src: RLE, ws=None, stream=None):
+    d, r = dst.struct(), src.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_transpose_rle(ctypes.byref(d), ctypes.byref(r), p, n, _stream(stream)),
+           "morph_transpose_rle")
+
+
+def morph_rlet_workspace_bytes(op, width, height, npages, s) -> int:
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    return int(_lib.morph_rlet_workspace_bytes(op, int(width), int(height), int(npages), _se(s)))
+
+
+def morph_rect_rlet(op, dst: RLE, src: RLE, s, ws=None, stream=None):
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    d, r = dst.struct(), src.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_rect_rlet(op, ctypes.byref(d), ctypes.byref(r), _se(s), p, n, _stream(stream)),
+           "morph_rect_rlet")
+
+
 class BatchPlan:
     """Many packed pages, each with its own operation and element, run as one
     persistent launch (morph_batch_plan_create / morph_batch_run)."""
@@ -472,4 +509,27 @@ def pack_to_rle(src: Bitmap, capacity=None, stream=None) -> RLE:
 def rle_to_pack(src: RLE, stride=None, stream=None) -> Bitmap:
     dst = Bitmap.empty(src.width, src.height, src.npages, stride=stride, device=src.row_ptr.device)
     morph_rle_to_pack(dst, src, stream)
+    return dst
+
+
+def transpose_packed(src: Bitmap, stream=None) -> Bitmap:
+    dst = Bitmap.empty(src.height, src.width, src.npages, device=src.words.device)
+    morph_transpose_packed(dst, src, stream)
+    return dst
+
+
+def transpose_rle(src: RLE, stream=None) -> RLE:
+    dst = RLE.empty(src.height, src.width, src.npages, device=src.row_ptr.device)
+    ws = _alloc_ws(morph_transpose_rle_workspace_bytes(src.width, src.height, src.npages), src.row_ptr.device)
+    morph_transpose_rle(dst, src, ws, stream)
+    return dst
+
+
+def rect_rlet(op: str, src: RLE, s, dst: RLE | None = None, stream=None) -> RLE:
+    """op in OPS on a run-length image by within-line operations and
+    transposition; same result as rect_rle."""
+    if dst is None:
+        dst = RLE.empty(src.width, src.height, src.npages, device=src.row_ptr.device)
+    ws = _alloc_ws(morph_rlet_workspace_bytes(op, src.width, src.height, src.npages, s), src.row_ptr.device)
+    morph_rect_rlet(op, dst, src, s, ws, stream)
     return dst

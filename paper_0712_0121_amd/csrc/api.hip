@@ -596,6 +596,160 @@ int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_s
     return MORPH_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------- transposition
+namespace morph {
+
+static bool transposed_shape(int dw, int dh, int dp, int sw, int sh, int sp)
+{
+    return dw == sh && dh == sw && dp == sp;
+}
+
+// Workspace of a run-length transpose: the transposed bitmap, then the
+// scratch of the re-encoding.
+static size_t transpose_rle_ws(int W, int H, int P)
+{
+    const size_t rows = (size_t)W * P;
+    return round256(image_bytes(H, (int)rows)) + round256(morph_pack_to_rle_workspace_bytes(H, (int)rows));
+}
+
+// Workspace of the transpose-based rectangle operation: one bitmap buffer
+// (the transposed image, later the image back in its own orientation), one
+// run-length buffer (the transposed runs; for opening and closing its run
+// array later holds the bitmap after the last within-line pass), the
+// re-encoding scratch and, for opening and closing, that last pass's
+// workspace.
+struct RletWs {
+    size_t bm, rp, runs, p2r, rowop, total;
+    long long cap;
+};
+
+static RletWs rlet_ws(int op, int W, int H, int P, morph_se_t se)
+{
+    RletWs w{};
+    const long long rowsT = (long long)W * P, rows = (long long)H * P;
+    w.bm = round256(std::max(image_bytes(H, (int)rowsT), image_bytes(W, (int)rows)));
+    w.cap = rowsT * ((H + 1) / 2);
+    w.rp = round256((size_t)(rowsT + 1) * 4);
+    w.runs = round256(std::max((size_t)w.cap * 8, image_bytes(W, (int)rows)));
+    w.p2r = round256(std::max(morph_pack_to_rle_workspace_bytes(H, (int)rowsT),
+                              morph_pack_to_rle_workspace_bytes(W, (int)rows)));
+    if (op == MORPH_OPEN || op == MORPH_CLOSE) {
+        const morph_se_t row{se.w, 1, se.cx, 0};
+        w.rowop = round256(morph_workspace_bytes(op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE, MORPH_PACKED,
+                                                 W, (int)rows, row));
+    }
+    w.total = w.bm + w.rp + w.runs + w.p2r + w.rowop;
+    return w;
+}
+
+// Rectangle operation by within-line operations and transposition: the
+// operation along the rows is applied while the runs are decoded into the
+// transposed bitmap, which is re-encoded; the operation along the former
+// columns is applied while those runs are decoded back.  Opening is E_w,
+// then the column opening, then D_w (closing the reverse): the row and
+// column passes of a rectangle commute, so two transpositions suffice, and
+// the last row pass runs on the decoded bitmap before it is re-encoded.
+static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se, char *ws,
+                    const RletWs &L, hipStream_t s)
+{
+    const int W = src.width, H = src.height, P = src.npages;
+    const morph_bitmap_t T1{(uint64_t *)ws, H, W, (H + 63) / 64, P};
+    const morph_rle_t R1{H, W, P, (int *)(ws + L.bm), (int *)(ws + L.bm + L.rp), L.cap};
+    const morph_bitmap_t T2{(uint64_t *)ws, W, H, (W + 63) / 64, P};
+    const morph_bitmap_t T3{(uint64_t *)(ws + L.bm + L.rp), W, H, (W + 63) / 64, P};
+    void *p2r = ws + L.bm + L.rp + L.runs;
+    const bool ero_first = (op == MORPH_ERODE || op == MORPH_OPEN);
+    const LineOp row{ero_first ? kLineErode : kLineDilate, se.w, se.cx, 0};
+    LineOp col{};
+    switch (op) {
+    case MORPH_ERODE: col = LineOp{kLineErode, se.h, se.cy, 0}; break;
+    case MORPH_DILATE: col = LineOp{kLineDilate, se.h, se.cy, 0}; break;
+    case MORPH_OPEN: col = LineOp{kLineOpen, se.h, se.cy, 0}; break;
+    default: col = LineOp{kLineOpen, se.h, se.h - 1 - se.cy, 1}; break;   // closing: the gaps' opening
+    }
+    hipError_t e = rle_decode_transposed(T1, src, row, s);
+    if (e == hipSuccess) e = rle_from_packed(R1, T1, p2r, s);
+    if (e == hipSuccess) e = rle_decode_transposed(T2, R1, col, s);
+    if (e == hipSuccess && (op == MORPH_ERODE || op == MORPH_DILATE)) e = rle_from_packed(dst, T2, p2r, s);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    if (op == MORPH_ERODE || op == MORPH_DILATE) return MORPH_OK;
+    const morph_se_t last{se.w, 1, se.cx, 0};
+    const int rc = rect_packed(op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE, &T3, &T2, last,
+                               L.rowop ? ws + L.bm + L.rp + L.runs + L.p2r : nullptr, L.rowop, s);
+    if (rc != MORPH_OK) return rc;
+    e = rle_from_packed(dst, T3, p2r, s);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+}  // namespace morph
+
+extern "C" {
+
+int morph_transpose_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_stream_t stream)
+{
+    if (!bitmap_ok(dst) || !bitmap_ok(src)) return MORPH_E_INVAL;
+    if (!transposed_shape(dst->width, dst->height, dst->npages, src->width, src->height, src->npages))
+        return MORPH_E_SHAPE;
+    if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
+    hipError_t e = packed_transpose(*dst, *src, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+size_t morph_transpose_rle_workspace_bytes(int32_t width, int32_t height, int32_t npages)
+{
+    if (width < 1 || height < 1 || npages < 1 || (long long)width * npages > 0x7fffffffLL) return 0;
+    return transpose_rle_ws(width, height, npages);
+}
+
+int morph_transpose_rle(const morph_rle_t *dst, const morph_rle_t *src, void *ws, size_t ws_bytes,
+                        morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !rle_ok(src)) return MORPH_E_INVAL;
+    if (!transposed_shape(dst->width, dst->height, dst->npages, src->width, src->height, src->npages))
+        return MORPH_E_SHAPE;
+    if (rle_alias(dst, src)) return MORPH_E_ALIAS;
+    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
+    const size_t need = morph_transpose_rle_workspace_bytes(src->width, src->height, src->npages);
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < need) return MORPH_E_WORKSPACE;
+    const int W = src->width, H = src->height, P = src->npages;
+    char *w = (char *)ws;
+    const morph_bitmap_t T{(uint64_t *)w, H, W, (H + 63) / 64, P};
+    hipError_t e = rle_decode_transposed(T, *src, LineOp{kLineNone, 1, 0, 0}, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = rle_from_packed(*dst, T, w + round256(image_bytes(H, W * P)), (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+size_t morph_rlet_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se)
+{
+    if (width < 1 || height < 1 || npages < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return 0;
+    if ((long long)width * npages > 0x7fffffffLL || (long long)height * npages > 0x7fffffffLL) return 0;
+    return rlet_ws(op, width, height, npages, se).total;
+}
+
+int morph_rect_rlet(int op, const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se, void *ws,
+                    size_t ws_bytes, morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !rle_ok(src) || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    if (rle_alias(dst, src)) return MORPH_E_ALIAS;
+    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
+    const int W = src->width, H = src->height, P = src->npages;
+    if ((long long)W * P > 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    const RletWs L = rlet_ws(op, W, H, P, se);
+    if (L.cap >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < L.total) return MORPH_E_WORKSPACE;
+    return rlet_run(op, *dst, *src, se, (char *)ws, L, (hipStream_t)stream);
+}
+
 int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
 {
     if (!rle_ok(r)) return MORPH_E_INVAL;
@@ -682,7 +836,8 @@ const char *morph_kernel_name(int k)
 {
     static const char *names[MORPH_K_COUNT] = {"rect_kernel", "rect_batch_kernel", "pack_to_rle_kernel",
                                                "rle_to_pack_kernel", "row_erode_kernel", "col_and_kernel",
-                                               "pack_rows_kernel"};
+                                               "pack_rows_kernel", "transpose_kernel",
+                                               "decode_transpose_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

@@ -9,6 +9,39 @@
 
 namespace morph {
 
+// Workgroups are dealt to the 8 XCDs round robin, and each XCD has its own
+// L2.  Kernels whose neighbouring rows share cache lines (a row and the row
+// K below it, or the partial lines where one row's runs end and the next
+// row's begin) take their rows from this logical index instead of
+// blockIdx.x: it gives every XCD one contiguous range of blocks.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned n = gridDim.x, b = blockIdx.x;
+    const unsigned x = b & 7u, q = n >> 3, rem = n & 7u;
+    return x * q + min(x, rem) + (b >> 3);
+}
+
+// Transposes the 64 x 64 bit matrix a wave holds one row per lane (bit k of
+// lane i is element (i, k)): afterwards lane i holds column i.  Six steps;
+// step j exchanges the off-diagonal j x j blocks of every 2j x 2j block
+// between lanes i and i ^ j.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t masks[6] = {0x00000000ffffffffull, 0x0000ffff0000ffffull, 0x00ff00ff00ff00ffull,
+                               0x0f0f0f0f0f0f0f0full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        const int j = 32 >> t;
+        const uint64_t m = masks[t];
+        const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, j, 64);
+        const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), j, 64);
+        const uint64_t y = ((uint64_t)yhi << 32) | ylo;
+        x = (lane & j) ? ((x & ~m) | ((y >> j) & m)) : ((x & m) | ((y << j) & ~m));
+    }
+    return x;
+}
+
 // ------------------------------------------------------------------ packed
 // Geometry of the fused band kernel (one workgroup = one tile).
 constexpr int kThreads = 512;          // threads per workgroup (large tiles)
@@ -63,6 +96,10 @@ hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev
 hipError_t launch_reset_counter(int *queue_dev, hipStream_t stream);
 int device_cu_count();
 
+// Transpose of every page of a packed bitmap (dst: width = src height,
+// height = src width).
+hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream);
+
 // ------------------------------------------------------------- run-length
 hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
                            hipStream_t stream);
@@ -71,6 +108,18 @@ size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t s
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 size_t scan_workspace(int64_t n);
+
+// Within-line operation applied to every run (or, with comp, every gap) of
+// a row as it is decoded: erosion shrinks an interval, dilation grows it,
+// opening does both.  w, c: element length and origin along the line.
+enum { kLineNone = 0, kLineErode = 1, kLineDilate = 2, kLineOpen = 3 };
+struct LineOp {
+    int mode, w, c, comp;
+};
+// Runs -> transposed packed bitmap (dst: width = src height, height = src
+// width), with op applied along the source rows.
+hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op,
+                                 hipStream_t stream);
 int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
 
 void set_hip_error(hipError_t e);

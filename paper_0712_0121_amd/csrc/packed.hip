@@ -519,6 +519,37 @@ __global__ void reset_counter_kernel(int *q)
 
 int cached_cu_count = 0;
 
+
+// ------------------------------------------------------------- transpose
+// One wave per 64 x 64 block of a page: lane i loads row 64k + i of word
+// column j, the butterfly turns the block, and lane i stores row 64j + i of
+// the transpose, word k.  Waves run k fastest and every XCD takes one
+// contiguous range, so an XCD reads whole word columns of a few pages
+// (each line from HBM once into its L2) and writes whole transposed rows.
+constexpr int kTransposeWaves = 4;
+
+__global__ __launch_bounds__(64 * kTransposeWaves) void transpose_kernel(
+    const uint64_t *__restrict__ src, int W, int H, int sstride, long long spw, uint64_t padmask,
+    uint64_t *__restrict__ dst, int dstride, long long dpw, int nw, int nk, long long total)
+{
+    const long long g = (long long)xcd_block() * kTransposeWaves + (threadIdx.x >> 6);
+    if (g >= total) return;                 // whole wave
+    const int lane = (int)(threadIdx.x & 63);
+    const long long per_page = (long long)nw * nk;
+    const int page = (int)(g / per_page);
+    const int u = (int)(g - (long long)page * per_page);
+    const int j = u / nk, k = u - j * nk;
+    const int y = 64 * k + lane;
+    uint64_t v = 0;
+    if (y < H) {
+        v = src[(long long)page * spw + (long long)y * sstride + j];
+        if (j == nw - 1) v &= padmask;
+    }
+    v = wave_transpose64(v);
+    const int x = 64 * j + lane;
+    if (x < W) dst[(long long)page * dpw + (long long)x * dstride + k] = v;
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -664,6 +695,23 @@ hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev
     hipLaunchKernelGGL(rect_batch_kernel, dim3(nblocks), dim3(kThreads), 0, stream, pages_dev,
                        tiles_dev, ntiles, queue_dev);
     trace_after(MORPH_K_RECT_BATCH, stream, alg_bytes);
+    return hipGetLastError();
+}
+
+hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream)
+{
+    const int W = src.width, H = src.height;
+    const int nw = (W + 63) / 64, nk = (H + 63) / 64;
+    const long long total = (long long)nw * nk * src.npages;
+    if (total <= 0) return hipSuccess;
+    const long long blocks = (total + kTransposeWaves - 1) / kTransposeWaves;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const uint64_t pad = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
+    trace_before(MORPH_K_TRANSPOSE, stream);
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(64 * kTransposeWaves), 0, stream,
+                       src.words, W, H, src.stride_words, (long long)src.stride_words * H, pad,
+                       dst.words, dst.stride_words, (long long)dst.stride_words * W, nw, nk, total);
+    trace_after(MORPH_K_TRANSPOSE, stream, 8.0 * src.npages * ((double)nw * H + (double)nk * W));
     return hipGetLastError();
 }
 

@@ -35,18 +35,6 @@ constexpr int kRowWaves = 4;                             // rows per workgroup (
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
-// Workgroups are dealt to the 8 XCDs round robin, and each XCD has its own
-// L2.  Kernels whose neighbouring rows share cache lines (a row and the row
-// K below it, or the partial lines where one row's runs end and the next
-// row's begin) take their rows from this logical index instead of
-// blockIdx.x: it gives every XCD one contiguous range of blocks.
-__device__ __forceinline__ unsigned xcd_block()
-{
-    const unsigned n = gridDim.x, b = blockIdx.x;
-    const unsigned x = b & 7u, q = n >> 3, rem = n & 7u;
-    return x * q + min(x, rem) + (b >> 3);
-}
-
 // Trace counters: runs read / written, spread over 256 slots (one 128-byte
 // line each) so that concurrent groups rarely add to the same address.
 constexpr int kTraceSlots = 256, kTraceStride = 16;
@@ -241,6 +229,84 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
     }
     words[(long long)page * page_words + (long long)y * stride + j] = v;
     if (trace && j == 0) trace_add(trace, (unsigned long long)(b1 - b0), 0);
+}
+
+// ------------------------------------------ runs -> transposed packed
+// One wave per 64 x 64 block: lane i decodes word j of row 64k + i the way
+// rle_to_pack does, after applying the row's within-line operation to each
+// run (or to each gap, for a complemented operation), the butterfly turns
+// the block, and lane i stores row 64j + i of the transpose, word k.  An
+// interval moves by at most w - 1 pixels, so the search starts at the first
+// interval whose raw end lies past x0 - (w - 1) and stops at the first
+// whose raw start lies at or past x1 + (w - 1).
+__device__ __forceinline__ bool line_interval(const LineOp &op, int W, int &s, int &e)
+{
+    const int right = op.w - 1 - op.c;
+    if (op.mode == kLineErode || op.mode == kLineOpen) {
+        const int ns = (s == 0) ? 0 : s + op.c;
+        const int ne = (e == W) ? W : e - right;
+        if (ns >= ne) return false;
+        s = ns;
+        e = ne;
+    }
+    if (op.mode == kLineDilate || op.mode == kLineOpen) {
+        s = max(0, s - op.c);
+        e = min(W, e + right);
+    }
+    return s < e;
+}
+
+constexpr int kDecodeWaves = 4;
+
+__global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
+    const int *__restrict__ row_ptr, const int *__restrict__ runs, long long cap, int W, int H,
+    int nw, int nk, long long total, uint64_t *__restrict__ dst, int dstride, long long dpw, LineOp op,
+    unsigned long long *trace)
+{
+    const long long g = (long long)xcd_block() * kDecodeWaves + (threadIdx.x >> 6);
+    if (g >= total) return;                 // whole wave
+    const int lane = lane_id();
+    const long long per_page = (long long)nw * nk;
+    const int page = (int)(g / per_page);
+    const int u = (int)(g - (long long)page * per_page);
+    const int j = u / nk, k = u - j * nk;
+    const int y = 64 * k + lane;
+    uint64_t v = 0;
+    if (y < H) {
+        const long long r = (long long)page * H + y;
+        const long long b0 = min((long long)max(row_ptr[r], 0), cap);
+        const long long b1 = max(b0, min((long long)row_ptr[r + 1], cap));
+        const int n = (int)(b1 - b0);
+        const int *rr = runs + 2 * b0;
+        const int ni = op.comp ? n + 1 : n;  // intervals: runs, or the n + 1 gaps
+        const int x0 = 64 * j, x1 = min(x0 + 64, W);
+        const int reach = op.w - 1;
+        auto istart = [&](int i) { return op.comp ? (i == 0 ? 0 : rr[2 * i - 1]) : rr[2 * i]; };
+        auto iend = [&](int i) { return op.comp ? (i == n ? W : rr[2 * i]) : rr[2 * i + 1]; };
+        int lo = 0, hi = ni;
+        while (lo < hi) {                   // first interval with end + reach > x0
+            const int mid = (lo + hi) >> 1;
+            if (iend(mid) + reach > x0) hi = mid; else lo = mid + 1;
+        }
+        for (int i = lo; i < ni; i++) {
+            int a = istart(i), b = iend(i);
+            if (a - reach >= x1) break;
+            if (!line_interval(op, W, a, b)) continue;
+            a = max(a, x0) - x0;
+            b = min(b, x1) - x0;
+            if (a >= b) continue;
+            const uint64_t hm = (b == 64) ? ~0ull : ((1ull << b) - 1);
+            v |= hm & ~((1ull << a) - 1);
+        }
+        if (op.comp) {
+            const int nb = x1 - x0;
+            v = ~v & ((nb == 64) ? ~0ull : ((1ull << nb) - 1));
+        }
+        if (trace && j == 0) trace_add(trace, (unsigned long long)n, 0);
+    }
+    v = wave_transpose64(v);
+    const int x = 64 * j + lane;
+    if (x < W) dst[(long long)page * dpw + (long long)x * dstride + k] = v;
 }
 
 // ------------------------------------------------- rows in two layouts
@@ -871,6 +937,25 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
                        (long long)dst.stride_words * dst.height, (long long)src.capacity,
                        trace_block(tr, MORPH_K_RLE_TO_PACK));
     trace_after(MORPH_K_RLE_TO_PACK, s, 8.0 * nw * R + 4.0 * (R + 1));
+    return hipGetLastError();
+}
+
+hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op,
+                                 hipStream_t s)
+{
+    const int W = src.width, H = src.height;
+    const int nw = (W + 63) / 64, nk = (H + 63) / 64;
+    const long long total = (long long)nw * nk * src.npages;
+    if (total <= 0) return hipSuccess;
+    const long long blocks = (total + kDecodeWaves - 1) / kDecodeWaves;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_DECODE_T, s);
+    hipLaunchKernelGGL(decode_transpose_kernel, dim3((unsigned)blocks), dim3(64 * kDecodeWaves), 0, s,
+                       src.row_ptr, src.runs, (long long)src.capacity, W, H, nw, nk, total, dst.words,
+                       dst.stride_words, (long long)dst.stride_words * W, op,
+                       trace_block(tr, MORPH_K_DECODE_T));
+    trace_after(MORPH_K_DECODE_T, s, 8.0 * (double)nk * W * src.npages + 4.0 * ((double)H * src.npages + 1));
     return hipGetLastError();
 }
 

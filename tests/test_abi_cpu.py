@@ -159,3 +159,53 @@ def test_batch_plan_argument_errors():
     assert M._lib.morph_batch_plan_create(ctypes.byref(h), desc, 1, None) == -8
     assert M._lib.morph_batch_plan_create(None, desc, 1, None) == -1
     assert M._lib.morph_batch_run(None, 1, None) == -1
+
+
+def test_transpose_argument_errors():
+    a, b = HostBuf(1 << 18), HostBuf(1 << 18)
+    W, H = 100, 30
+    tp = lambda d, s: M._lib.morph_transpose_packed(ctypes.byref(d), ctypes.byref(s), None)
+    assert tp(bitmap(a, W, H), bitmap(b, W, H)) == -2              # not transposed sizes
+    assert tp(bitmap(a, H, W, npages=2), bitmap(b, W, H)) == -2
+    assert tp(bitmap(a, H, W), bitmap(a, W, H)) == -3
+    assert tp(bitmap(a, H, W, off=4), bitmap(b, W, H)) == -1
+    assert tp(M.morph_bitmap_t(None, H, W, 1, 1), bitmap(b, W, H)) == -1
+    tr = lambda d, s, ws=None, n=0: M._lib.morph_transpose_rle(ctypes.byref(d), ctypes.byref(s), ws, n, None)
+    capT = M.morph_rle_max_runs(H, W)
+    assert tr(rle(a, H, W, capT), rle(b, W, H, 10)) == -4
+    assert tr(rle(a, W, H, capT), rle(b, W, H, 10)) == -2
+    assert tr(rle(a, H, W, capT - 1), rle(b, W, H, 10)) == -6
+    assert tr(rle(a, H, W, capT), rle(a, W, H, 10)) == -3
+    need = M.morph_transpose_rle_workspace_bytes(W, H, 1)
+    assert need >= W * ((H + 63) // 64) * 8
+    ws = HostBuf(need + 512)
+    aligned = (ws.ptr + 255) & ~255
+    assert tr(rle(a, H, W, capT), rle(b, W, H, 10), aligned, need - 1) == -4
+    assert tr(rle(a, H, W, capT), rle(b, W, H, 10), aligned + 8, need) == -4     # not 256-byte aligned
+
+
+@pytest.mark.parametrize("op", M.OPS)
+def test_rlet_argument_errors(op):
+    a, b = HostBuf(1 << 20), HostBuf(1 << 20)
+    W, H = 200, 30
+    cap = M.morph_rle_max_runs(W, H)
+    k = M.OPS.index(op)
+    se = M.morph_se_t(5, 3, 2, 1)
+    call = lambda d, s, se=se, ws=None, n=0, k=k: M._lib.morph_rect_rlet(k, ctypes.byref(d), ctypes.byref(s), se,
+                                                                         ws, n, None)
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), M.morph_se_t(5, 3, 2, 3)) == -1
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), k=7) == -1
+    assert call(rle(a, W, H, cap), rle(b, W, H + 1, cap)) == -2
+    assert call(rle(a, W, H, cap), rle(a, W, H, cap)) == -3
+    assert call(rle(a, W, H, cap - 1), rle(b, W, H, cap)) == -6
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap)) == -4
+    need = M.morph_rlet_workspace_bytes(op, W, H, 1, (5, 3, 2, 1))
+    # the transposed image's worst case: W rows of ceil(H/2) runs
+    assert need >= W * ((H + 1) // 2) * 8
+    ws = HostBuf(need + 512)
+    aligned = (ws.ptr + 255) & ~255
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, aligned, need - 1) == -4
+    # a transposed worst case beyond 2^31 runs
+    huge_a = M.morph_rle_t(100000, 60000, 1, 1 << 40, (1 << 40) + (1 << 30), 10**10)
+    huge_b = M.morph_rle_t(100000, 60000, 1, 2 << 40, (2 << 40) + (1 << 30), 10**10)
+    assert call(huge_a, huge_b) == -8
