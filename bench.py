@@ -242,6 +242,61 @@ def bench_serving(M, dev, seconds):
             "load_points": points}
 
 
+def bench_transpose(M, dev, src, rle_ms_per_op):
+    """Transposition and the transpose-based ("rlet") rectangle operations on
+    the letter batch: the packed transpose, the run-length transpose, and the
+    20 operations on runs by within-line passes plus transposition, beside
+    the run-length path's own times for the same operations."""
+    import torch
+    W, H, B = src.width, src.height, src.npages
+    nw, nk = (W + 63) // 64, (H + 63) // 64
+    tdst = M.Bitmap.empty(H, W, B, device=dev)
+    t_pk = time_ms(lambda: M.morph_transpose_packed(tdst, src), 5)
+    alg_pk = 8 * B * (nw * H + nk * W)
+    del tdst
+    r_in = M.RLE.empty(W, H, B, device=dev)
+    ws_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * B), dtype=torch.uint8, device=dev)
+    M.morph_pack_to_rle(r_in, src, ws_p2r)
+    del ws_p2r
+    r_t = M.RLE.empty(H, W, B, device=dev)
+    ws_t = torch.empty(M.morph_transpose_rle_workspace_bytes(W, H, B), dtype=torch.uint8, device=dev)
+    t_rt = time_ms(lambda: M.morph_transpose_rle(r_t, r_in, ws_t), 3)
+    with M.Trace() as tr:
+        M.morph_transpose_rle(r_t, r_in, ws_t)
+    runs_in, runs_t = int(r_in.row_ptr[-1].item()), int(r_t.row_ptr[-1].item())
+    del r_t, ws_t
+    torch.cuda.empty_cache()
+    r_out = M.RLE.empty(W, H, B, device=dev)
+    ws_n = max(M.morph_rlet_workspace_bytes(op, W, H, B, se) for op in OPS for _, se in LETTER_SES)
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=dev)
+    per = {}
+    for name, se in LETTER_SES:
+        for op in OPS:
+            per["%s %s" % (op, name)] = round(time_ms(lambda: M.morph_rect_rlet(op, r_out, r_in, se, ws), 2), 4)
+    with M.Trace() as tr2:
+        for name, se in LETTER_SES:
+            for op in OPS:
+                M.morph_rect_rlet(op, r_out, r_in, se, ws)
+    del r_out, ws, r_in
+    torch.cuda.empty_cache()
+    kern = lambda res: {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
+                            "gbs": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] else None}
+                        for k, v in res.items()}
+    px = W * H * B
+    rlet_ms = sum(per.values())
+    out = {"pages": B,
+           "packed_transpose": {"ms": t_pk, "alg_bytes": alg_pk, "gbs": alg_pk / (t_pk / 1e3) / 1e9,
+                                "hbm_frac": alg_pk / (t_pk / 1e3) / 1e9 / HBM_PEAK_GBS},
+           "rle_transpose": {"ms": t_rt, "gpixel_s": px / (t_rt / 1e3) / 1e9, "runs_in": runs_in,
+                             "runs_out": runs_t, "kernels": kern(tr.result)},
+           "rlet": {"ms_ops": rlet_ms, "gpixel_s": len(per) * px / (rlet_ms / 1e3) / 1e9, "ms_per_op": per,
+                    "kernels": kern(tr2.result)}}
+    if rle_ms_per_op:
+        out["rlet"]["rle_ms_per_op"] = rle_ms_per_op
+        out["rlet"]["rle_ms_ops"] = sum(rle_ms_per_op.values())
+    return out
+
+
 def bench_repr(M, dev, tuner):
     """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
     (conversions included), as the autotuner records it."""
@@ -454,6 +509,7 @@ def main():
         out["batched"] = bench_batched(M, dev, tuner)
         out["repr_choice"] = bench_repr(M, dev, tuner)
         out["serving"] = bench_serving(M, dev, args.serve_seconds)
+        out["transpose"] = bench_transpose(M, dev, src, breakdown.get("rle", {}).get("ms_per_op"))
         try:
             tuner.save()
         except OSError:

@@ -21,24 +21,48 @@ __device__ __forceinline__ unsigned xcd_block()
     return x * q + min(x, rem) + (b >> 3);
 }
 
+// Value of lane (this lane ^ J) for J = 1, 2, 4, 8 (DPP moves inside the
+// 16-lane rows), 16 (swizzle inside 32-lane halves) and 32 (permute).
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
+{
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+    } else if constexpr (J == 4) {
+        // row_ror:n reads lane (i - n) mod 16 of the row
+        const uint32_t below = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);  // i - 4
+        const uint32_t above = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xf, 0xf, false);  // i + 4
+        return (threadIdx.x & 4) ? below : above;
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    } else if constexpr (J == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);                       // xor 16
+    } else {
+        return (uint32_t)__shfl_xor((int)v, 32, 64);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t transpose_step(uint64_t x, uint64_t m)
+{
+    const uint64_t y = ((uint64_t)lane_xor<J>((uint32_t)(x >> 32)) << 32) | lane_xor<J>((uint32_t)x);
+    return (threadIdx.x & J) ? ((x & ~m) | ((y >> J) & m)) : ((x & m) | ((y << J) & ~m));
+}
+
 // Transposes the 64 x 64 bit matrix a wave holds one row per lane (bit k of
 // lane i is element (i, k)): afterwards lane i holds column i.  Six steps;
-// step j exchanges the off-diagonal j x j blocks of every 2j x 2j block
-// between lanes i and i ^ j.
+// step J exchanges the off-diagonal J x J blocks of every 2J x 2J block
+// between lanes i and i ^ J.  Every lane of the wave must be active.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x)
 {
-    const int lane = (int)(threadIdx.x & 63);
-    const uint64_t masks[6] = {0x00000000ffffffffull, 0x0000ffff0000ffffull, 0x00ff00ff00ff00ffull,
-                               0x0f0f0f0f0f0f0f0full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int t = 0; t < 6; t++) {
-        const int j = 32 >> t;
-        const uint64_t m = masks[t];
-        const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, j, 64);
-        const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), j, 64);
-        const uint64_t y = ((uint64_t)yhi << 32) | ylo;
-        x = (lane & j) ? ((x & ~m) | ((y >> j) & m)) : ((x & m) | ((y << j) & ~m));
-    }
+    x = transpose_step<32>(x, 0x00000000ffffffffull);
+    x = transpose_step<16>(x, 0x0000ffff0000ffffull);
+    x = transpose_step<8>(x, 0x00ff00ff00ff00ffull);
+    x = transpose_step<4>(x, 0x0f0f0f0f0f0f0f0full);
+    x = transpose_step<2>(x, 0x3333333333333333ull);
+    x = transpose_step<1>(x, 0x5555555555555555ull);
     return x;
 }
 

@@ -521,33 +521,86 @@ int cached_cu_count = 0;
 
 
 // ------------------------------------------------------------- transpose
-// One wave per 64 x 64 block of a page: lane i loads row 64k + i of word
-// column j, the butterfly turns the block, and lane i stores row 64j + i of
-// the transpose, word k.  Waves run k fastest and every XCD takes one
-// contiguous range, so an XCD reads whole word columns of a few pages
-// (each line from HBM once into its L2) and writes whole transposed rows.
-constexpr int kTransposeWaves = 4;
+// One workgroup of 256 threads per tile of kTrRows rows x kTrWords words of
+// a page (blocks of 64 x 64 pixels).  Each thread loads whole tile rows,
+// kTrWords contiguous words each, into LDS; then each wave turns the
+// blocks of kTrWords / 4 word columns: for each it runs the butterfly on
+// the kTrRows / 64 blocks below each other, after which lane i holds that
+// many consecutive words of transposed row 64j + i and stores them
+// contiguously.  Rows are padded by one word in LDS so that the column
+// reads of the butterfly input spread over the banks.
+constexpr int kTrRows = 512, kTrWords = 8, kTrPad = kTrWords + 1;
+constexpr int kTrRowsPerThread = kTrRows / 256, kTrColsPerWave = kTrWords / 4, kTrBlocks = kTrRows / 64;
 
-__global__ __launch_bounds__(64 * kTransposeWaves) void transpose_kernel(
+__global__ __launch_bounds__(256) void transpose_kernel(
     const uint64_t *__restrict__ src, int W, int H, int sstride, long long spw, uint64_t padmask,
-    uint64_t *__restrict__ dst, int dstride, long long dpw, int nw, int nk, long long total)
+    uint64_t *__restrict__ dst, int dstride, long long dpw, int nw, int nk, int tiles_y, int tiles_x,
+    long long ntiles)
 {
-    const long long g = (long long)xcd_block() * kTransposeWaves + (threadIdx.x >> 6);
-    if (g >= total) return;                 // whole wave
-    const int lane = (int)(threadIdx.x & 63);
-    const long long per_page = (long long)nw * nk;
-    const int page = (int)(g / per_page);
-    const int u = (int)(g - (long long)page * per_page);
-    const int j = u / nk, k = u - j * nk;
-    const int y = 64 * k + lane;
-    uint64_t v = 0;
-    if (y < H) {
-        v = src[(long long)page * spw + (long long)y * sstride + j];
-        if (j == nw - 1) v &= padmask;
+    __shared__ uint64_t tile[kTrRows * kTrPad];
+    const long long t = xcd_block();
+    if (t >= ntiles) return;                // whole workgroup
+    const long long per_page = (long long)tiles_y * tiles_x;
+    const int page = (int)(t / per_page);
+    const int u = (int)(t - (long long)page * per_page);
+    const int tx = u / tiles_y, ty = u - tx * tiles_y;     // row tiles fastest
+    const int y0 = ty * kTrRows, j0 = tx * kTrWords;
+    const int nj = min(kTrWords, nw - j0);
+    const uint64_t *sp = src + (long long)page * spw;
+#pragma unroll
+    for (int h = 0; h < kTrRowsPerThread; h++) {
+        const int r = (int)threadIdx.x + 256 * h, y = y0 + r;
+        uint64_t v[kTrWords];
+        if (y < H && nj == kTrWords) {
+            const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(sp + (long long)y * sstride + j0);
+            if ((((uintptr_t)q) & 15) == 0) {
+#pragma unroll
+                for (int c = 0; c < kTrWords / 2; c++) {
+                    const ulonglong2 w2 = q[c];
+                    v[2 * c] = w2.x;
+                    v[2 * c + 1] = w2.y;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < kTrWords; c++) v[c] = sp[(long long)y * sstride + j0 + c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kTrWords; c++)
+                v[c] = (y < H && c < nj) ? sp[(long long)y * sstride + j0 + c] : 0ull;
+        }
+        if (j0 + kTrWords >= nw) {          // the last word of the row: pad bits are 0
+            const int c = nw - 1 - j0;
+#pragma unroll
+            for (int cc = 0; cc < kTrWords; cc++)
+                if (cc == c) v[cc] &= padmask;
+        }
+#pragma unroll
+        for (int c = 0; c < kTrWords; c++) tile[r * kTrPad + c] = v[c];
     }
-    v = wave_transpose64(v);
-    const int x = 64 * j + lane;
-    if (x < W) dst[(long long)page * dpw + (long long)x * dstride + k] = v;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int nkk = min(kTrBlocks, nk - y0 / 64);          // row blocks of this tile
+#pragma unroll
+    for (int h = 0; h < kTrColsPerWave; h++) {
+        const int jj = kTrColsPerWave * wv + h;     // word column of the tile
+        uint64_t o[kTrBlocks];
+#pragma unroll
+        for (int kk = 0; kk < kTrBlocks; kk++) o[kk] = wave_transpose64(tile[(64 * kk + lane) * kTrPad + jj]);
+        const int x = 64 * (j0 + jj) + lane;
+        if (jj < nj && x < W) {
+            uint64_t *dp = dst + (long long)page * dpw + (long long)x * dstride + y0 / 64;
+            if (nkk == kTrBlocks && (((uintptr_t)dp) & 15) == 0) {
+                ulonglong2 *q = reinterpret_cast<ulonglong2 *>(dp);
+#pragma unroll
+                for (int c = 0; c < kTrBlocks / 2; c++) q[c] = make_ulonglong2(o[2 * c], o[2 * c + 1]);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < kTrBlocks; kk++)
+                    if (kk < nkk) dp[kk] = o[kk];
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -702,15 +755,15 @@ hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src
 {
     const int W = src.width, H = src.height;
     const int nw = (W + 63) / 64, nk = (H + 63) / 64;
-    const long long total = (long long)nw * nk * src.npages;
-    if (total <= 0) return hipSuccess;
-    const long long blocks = (total + kTransposeWaves - 1) / kTransposeWaves;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int tiles_y = (H + kTrRows - 1) / kTrRows, tiles_x = (nw + kTrWords - 1) / kTrWords;
+    const long long ntiles = (long long)tiles_y * tiles_x * src.npages;
+    if (ntiles <= 0) return hipSuccess;
+    if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
     const uint64_t pad = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
     trace_before(MORPH_K_TRANSPOSE, stream);
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(64 * kTransposeWaves), 0, stream,
-                       src.words, W, H, src.stride_words, (long long)src.stride_words * H, pad,
-                       dst.words, dst.stride_words, (long long)dst.stride_words * W, nw, nk, total);
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)ntiles), dim3(256), 0, stream, src.words, W, H,
+                       src.stride_words, (long long)src.stride_words * H, pad, dst.words, dst.stride_words,
+                       (long long)dst.stride_words * W, nw, nk, tiles_y, tiles_x, ntiles);
     trace_after(MORPH_K_TRANSPOSE, stream, 8.0 * src.npages * ((double)nw * H + (double)nk * W));
     return hipGetLastError();
 }

@@ -232,13 +232,17 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
 }
 
 // ------------------------------------------ runs -> transposed packed
-// One wave per 64 x 64 block: lane i decodes word j of row 64k + i the way
-// rle_to_pack does, after applying the row's within-line operation to each
-// run (or to each gap, for a complemented operation), the butterfly turns
-// the block, and lane i stores row 64j + i of the transpose, word k.  An
-// interval moves by at most w - 1 pixels, so the search starts at the first
-// interval whose raw end lies past x0 - (w - 1) and stops at the first
-// whose raw start lies at or past x1 + (w - 1).
+// One wave per 64-row block and strip of kDecodeStrip words.  Lane i streams
+// the runs of row 64k + i once, in order (one 8-byte load per run), turns
+// each run -- or each gap, for a complemented operation -- into an interval
+// by the row's within-line operation, and ORs the intervals into the word
+// being built; an interval that reaches past the word is kept in registers
+// for the next one.  The operation moves starts and ends monotonically, so
+// once an interval reaches past the word every later one's part of the
+// word lies inside it.  For every word the butterfly turns the 64 x 64
+// block and lane i stores row 64j + i of the transpose, word k.  Waves run
+// k fastest: neighbouring waves read neighbouring rows and write
+// neighbouring words of the same transposed rows.
 __device__ __forceinline__ bool line_interval(const LineOp &op, int W, int &s, int &e)
 {
     const int right = op.w - 1 - op.c;
@@ -257,56 +261,90 @@ __device__ __forceinline__ bool line_interval(const LineOp &op, int W, int &s, i
 }
 
 constexpr int kDecodeWaves = 4;
+constexpr int kDecodeStrip = 8;         // words of a row one wave decodes
 
 __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
     const int *__restrict__ row_ptr, const int *__restrict__ runs, long long cap, int W, int H,
-    int nw, int nk, long long total, uint64_t *__restrict__ dst, int dstride, long long dpw, LineOp op,
-    unsigned long long *trace)
+    int nw, int nk, int nstrips, long long total, uint64_t *__restrict__ dst, int dstride, long long dpw,
+    LineOp op, unsigned long long *trace)
 {
     const long long g = (long long)xcd_block() * kDecodeWaves + (threadIdx.x >> 6);
     if (g >= total) return;                 // whole wave
     const int lane = lane_id();
-    const long long per_page = (long long)nw * nk;
+    const long long per_page = (long long)nstrips * nk;
     const int page = (int)(g / per_page);
     const int u = (int)(g - (long long)page * per_page);
-    const int j = u / nk, k = u - j * nk;
+    const int strip = u / nk, k = u - strip * nk;
+    const int j0 = strip * kDecodeStrip, j1 = min(j0 + kDecodeStrip, nw);
     const int y = 64 * k + lane;
-    uint64_t v = 0;
-    if (y < H) {
+    const bool live = y < H;
+    const int reach = op.w - 1;
+    const int2 *rr = reinterpret_cast<const int2 *>(runs);
+    int n = 0, ni = 0, i = 0, prev_e = 0;   // next interval to load; gaps: end of the run before it
+    if (live) {
         const long long r = (long long)page * H + y;
         const long long b0 = min((long long)max(row_ptr[r], 0), cap);
         const long long b1 = max(b0, min((long long)row_ptr[r + 1], cap));
-        const int n = (int)(b1 - b0);
-        const int *rr = runs + 2 * b0;
-        const int ni = op.comp ? n + 1 : n;  // intervals: runs, or the n + 1 gaps
-        const int x0 = 64 * j, x1 = min(x0 + 64, W);
-        const int reach = op.w - 1;
-        auto istart = [&](int i) { return op.comp ? (i == 0 ? 0 : rr[2 * i - 1]) : rr[2 * i]; };
-        auto iend = [&](int i) { return op.comp ? (i == n ? W : rr[2 * i]) : rr[2 * i + 1]; };
-        int lo = 0, hi = ni;
-        while (lo < hi) {                   // first interval with end + reach > x0
-            const int mid = (lo + hi) >> 1;
-            if (iend(mid) + reach > x0) hi = mid; else lo = mid + 1;
+        n = (int)(b1 - b0);
+        rr += b0;
+        ni = op.comp ? n + 1 : n;           // intervals: runs, or the n + 1 gaps
+        if (trace && strip == 0) trace_add(trace, (unsigned long long)n, 0);
+        // first interval whose raw end + reach passes the strip's first pixel
+        const int x0 = 64 * j0;
+        int hi = ni;
+        while (i < hi) {
+            const int mid = (i + hi) >> 1;
+            const int e = op.comp ? (mid == n ? W : rr[mid].x) : rr[mid].y;
+            if (e + reach > x0) hi = mid; else i = mid + 1;
         }
-        for (int i = lo; i < ni; i++) {
-            int a = istart(i), b = iend(i);
-            if (a - reach >= x1) break;
-            if (!line_interval(op, W, a, b)) continue;
-            a = max(a, x0) - x0;
-            b = min(b, x1) - x0;
-            if (a >= b) continue;
-            const uint64_t hm = (b == 64) ? ~0ull : ((1ull << b) - 1);
-            v |= hm & ~((1ull << a) - 1);
-        }
-        if (op.comp) {
-            const int nb = x1 - x0;
-            v = ~v & ((nb == 64) ? ~0ull : ((1ull << nb) - 1));
-        }
-        if (trace && j == 0) trace_add(trace, (unsigned long long)n, 0);
+        if (op.comp && i > 0) prev_e = rr[i - 1].y;
     }
-    v = wave_transpose64(v);
-    const int x = 64 * j + lane;
-    if (x < W) dst[(long long)page * dpw + (long long)x * dstride + k] = v;
+    bool have = false;                      // (a, b): the interval carried into the next word
+    int a = 0, b = 0;
+    uint64_t *out = dst + (long long)page * dpw + k;
+    for (int j = j0; j < j1; j++) {
+        uint64_t v = 0;
+        if (live) {
+            const int x0 = 64 * j, x1 = min(x0 + 64, W);
+            for (;;) {
+                if (!have) {
+                    if (i >= ni) break;
+                    int s, e;
+                    if (op.comp) {
+                        s = prev_e;
+                        if (i < n) {
+                            const int2 q = rr[i];
+                            e = q.x;
+                            prev_e = q.y;
+                        } else {
+                            e = W;
+                        }
+                    } else {
+                        const int2 q = rr[i];
+                        s = q.x;
+                        e = q.y;
+                    }
+                    i++;
+                    if (!line_interval(op, W, s, e)) continue;
+                    a = s;
+                    b = e;
+                    have = true;
+                }
+                if (a >= x1) break;         // starts in a later word
+                const int lo = max(a, x0) - x0, hi = min(b, x1) - x0;
+                if (lo < hi) v |= ((hi == 64) ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+                if (b > x1) break;          // reaches into the next word
+                have = false;
+            }
+            if (op.comp) {
+                const int nb = x1 - x0;
+                v = ~v & ((nb == 64) ? ~0ull : ((1ull << nb) - 1));
+            }
+        }
+        v = wave_transpose64(v);
+        const int x = 64 * j + lane;
+        if (x < W) out[(long long)x * dstride] = v;
+    }
 }
 
 // ------------------------------------------------- rows in two layouts
@@ -945,14 +983,15 @@ hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &s
 {
     const int W = src.width, H = src.height;
     const int nw = (W + 63) / 64, nk = (H + 63) / 64;
-    const long long total = (long long)nw * nk * src.npages;
+    const int nstrips = (nw + kDecodeStrip - 1) / kDecodeStrip;
+    const long long total = (long long)nstrips * nk * src.npages;
     if (total <= 0) return hipSuccess;
     const long long blocks = (total + kDecodeWaves - 1) / kDecodeWaves;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_DECODE_T, s);
     hipLaunchKernelGGL(decode_transpose_kernel, dim3((unsigned)blocks), dim3(64 * kDecodeWaves), 0, s,
-                       src.row_ptr, src.runs, (long long)src.capacity, W, H, nw, nk, total, dst.words,
+                       src.row_ptr, src.runs, (long long)src.capacity, W, H, nw, nk, nstrips, total, dst.words,
                        dst.stride_words, (long long)dst.stride_words * W, op,
                        trace_block(tr, MORPH_K_DECODE_T));
     trace_after(MORPH_K_DECODE_T, s, 8.0 * (double)nk * W * src.npages + 4.0 * ((double)H * src.npages + 1));
