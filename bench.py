@@ -42,8 +42,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
-    ap.add_argument("--only", choices=["all", "packed", "rle"], default="all",
-                    help="restrict the step (for profiling); the JSON value needs 'all'")
+    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose"], default="all",
+                    help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose' "
+                         "prints only the transposition measurements")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -327,6 +328,15 @@ def main():
     words_pool = [torch.from_numpy(p.words().view(np.int64)) for p in pool]
     host = torch.cat([words_pool[i % len(pool)] for i in range(B)], dim=0)
     src = M.Bitmap(host.to(dev), W, H, B)
+    if args.only == "transpose":
+        del host
+        res = bench_transpose(M, dev, src, None)
+        # the elementwise copy whose HBM counters calibrate the profiles
+        cal = torch.empty_like(src.words)
+        torch.bitwise_or(src.words, 0, out=cal)
+        torch.cuda.synchronize()
+        print(json.dumps({"transpose": res}), flush=True)
+        return
     dst = M.Bitmap.empty(W, H, B, device=dev)
     back = M.Bitmap.empty(W, H, B, device=dev)
     del host

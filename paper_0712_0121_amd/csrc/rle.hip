@@ -232,17 +232,18 @@ __global__ __launch_bounds__(256) void rle_to_pack_kernel(const int *__restrict_
 }
 
 // ------------------------------------------ runs -> transposed packed
-// One wave per 64-row block and strip of kDecodeStrip words.  Lane i streams
-// the runs of row 64k + i once, in order (one 8-byte load per run), turns
-// each run -- or each gap, for a complemented operation -- into an interval
-// by the row's within-line operation, and ORs the intervals into the word
-// being built; an interval that reaches past the word is kept in registers
-// for the next one.  The operation moves starts and ends monotonically, so
-// once an interval reaches past the word every later one's part of the
-// word lies inside it.  For every word the butterfly turns the 64 x 64
-// block and lane i stores row 64j + i of the transpose, word k.  Waves run
-// k fastest: neighbouring waves read neighbouring rows and write
-// neighbouring words of the same transposed rows.
+// One workgroup of kDecodeWaves waves per group of kDecodeWaves 64-row
+// blocks and strip of kDecodeStrip words.  Lane i of wave q streams the
+// runs of row 64(k0 + q) + i once, in order (one 8-byte load per run),
+// turns each run -- or each gap, for a complemented operation -- into an
+// interval by the row's within-line operation, and ORs the intervals into
+// the word being built; an interval that reaches past the word is kept in
+// registers for the next one.  The operation moves starts and ends
+// monotonically, so once an interval reaches past the word every later
+// one's part of the word lies inside it.  For every word the butterfly
+// turns the 64 x 64 block; the transposed words wait in LDS until the
+// workgroup has all of them, and each thread then stores kDecodeWaves
+// consecutive words (64 bytes) of one transposed row.
 __device__ __forceinline__ bool line_interval(const LineOp &op, int W, int &s, int &e)
 {
     const int right = op.w - 1 - op.c;
@@ -260,21 +261,24 @@ __device__ __forceinline__ bool line_interval(const LineOp &op, int W, int &s, i
     return s < e;
 }
 
-constexpr int kDecodeWaves = 4;
-constexpr int kDecodeStrip = 8;         // words of a row one wave decodes
+constexpr int kDecodeWaves = 8;         // row blocks per workgroup = words per stored segment
+constexpr int kDecodeStrip = 8;         // words of a row one workgroup decodes
+constexpr int kDecodePad = kDecodeWaves + 1;
 
 __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
     const int *__restrict__ row_ptr, const int *__restrict__ runs, long long cap, int W, int H,
-    int nw, int nk, int nstrips, long long total, uint64_t *__restrict__ dst, int dstride, long long dpw,
-    LineOp op, unsigned long long *trace)
+    int nw, int nk, int nstrips, int kgroups, long long total, uint64_t *__restrict__ dst, int dstride,
+    long long dpw, LineOp op, unsigned long long *trace)
 {
-    const long long g = (long long)xcd_block() * kDecodeWaves + (threadIdx.x >> 6);
-    if (g >= total) return;                 // whole wave
-    const int lane = lane_id();
-    const long long per_page = (long long)nstrips * nk;
+    __shared__ uint64_t stage[kDecodeStrip * 64 * kDecodePad];
+    const long long g = xcd_block();
+    if (g >= total) return;                 // whole workgroup
+    const int lane = lane_id(), q = (int)(threadIdx.x >> 6);
+    const long long per_page = (long long)nstrips * kgroups;
     const int page = (int)(g / per_page);
     const int u = (int)(g - (long long)page * per_page);
-    const int strip = u / nk, k = u - strip * nk;
+    const int strip = u / kgroups, kg = u - strip * kgroups;
+    const int k0 = kg * kDecodeWaves, k = k0 + q;
     const int j0 = strip * kDecodeStrip, j1 = min(j0 + kDecodeStrip, nw);
     const int y = 64 * k + lane;
     const bool live = y < H;
@@ -301,7 +305,6 @@ __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
     }
     bool have = false;                      // (a, b): the interval carried into the next word
     int a = 0, b = 0;
-    uint64_t *out = dst + (long long)page * dpw + k;
     for (int j = j0; j < j1; j++) {
         uint64_t v = 0;
         if (live) {
@@ -313,16 +316,16 @@ __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
                     if (op.comp) {
                         s = prev_e;
                         if (i < n) {
-                            const int2 q = rr[i];
-                            e = q.x;
-                            prev_e = q.y;
+                            const int2 t = rr[i];
+                            e = t.x;
+                            prev_e = t.y;
                         } else {
                             e = W;
                         }
                     } else {
-                        const int2 q = rr[i];
-                        s = q.x;
-                        e = q.y;
+                        const int2 t = rr[i];
+                        s = t.x;
+                        e = t.y;
                     }
                     i++;
                     if (!line_interval(op, W, s, e)) continue;
@@ -341,9 +344,24 @@ __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
                 v = ~v & ((nb == 64) ? ~0ull : ((1ull << nb) - 1));
             }
         }
-        v = wave_transpose64(v);
-        const int x = 64 * j + lane;
-        if (x < W) out[(long long)x * dstride] = v;
+        v = wave_transpose64(v);            // lane: transposed row 64j + lane, word k
+        stage[((j - j0) * 64 + lane) * kDecodePad + q] = v;
+    }
+    __syncthreads();
+    // thread t: transposed row 64(j0 + t / 64) + t % 64, words k0 .. k0 + kDecodeWaves - 1
+    const int jj = (int)(threadIdx.x >> 6);
+    const int x = 64 * (j0 + jj) + lane;
+    const int nkk = min(kDecodeWaves, nk - k0);
+    if (j0 + jj < j1 && x < W) {
+        const uint64_t *sv = stage + (jj * 64 + lane) * kDecodePad;
+        uint64_t *dp = dst + (long long)page * dpw + (long long)x * dstride + k0;
+        if (nkk == kDecodeWaves && (((uintptr_t)dp) & 15) == 0) {
+            ulonglong2 *d2 = reinterpret_cast<ulonglong2 *>(dp);
+#pragma unroll
+            for (int c = 0; c < kDecodeWaves / 2; c++) d2[c] = make_ulonglong2(sv[2 * c], sv[2 * c + 1]);
+        } else {
+            for (int c = 0; c < nkk; c++) dp[c] = sv[c];
+        }
     }
 }
 
@@ -984,14 +1002,15 @@ hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &s
     const int W = src.width, H = src.height;
     const int nw = (W + 63) / 64, nk = (H + 63) / 64;
     const int nstrips = (nw + kDecodeStrip - 1) / kDecodeStrip;
-    const long long total = (long long)nstrips * nk * src.npages;
+    const int kgroups = (nk + kDecodeWaves - 1) / kDecodeWaves;
+    const long long total = (long long)nstrips * kgroups * src.npages;
     if (total <= 0) return hipSuccess;
-    const long long blocks = (total + kDecodeWaves - 1) / kDecodeWaves;
+    const long long blocks = total;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_DECODE_T, s);
     hipLaunchKernelGGL(decode_transpose_kernel, dim3((unsigned)blocks), dim3(64 * kDecodeWaves), 0, s,
-                       src.row_ptr, src.runs, (long long)src.capacity, W, H, nw, nk, nstrips, total, dst.words,
+                       src.row_ptr, src.runs, (long long)src.capacity, W, H, nw, nk, nstrips, kgroups, total, dst.words,
                        dst.stride_words, (long long)dst.stride_words * W, op,
                        trace_block(tr, MORPH_K_DECODE_T));
     trace_after(MORPH_K_DECODE_T, s, 8.0 * (double)nk * W * src.npages + 4.0 * ((double)H * src.npages + 1));

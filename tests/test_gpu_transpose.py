@@ -192,3 +192,44 @@ def test_trace_names_the_transpose_kernels():
     n = int(src.nruns())
     # algorithmic bytes of the first decode: the runs and row counts read, the transposed words written
     assert res["decode_transpose_kernel"]["bytes"] >= 8 * n + 8 * 300 * 2
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+def test_rlet_letter_batch_as_timed(op):
+    """The benchmark's batch: 256 stacked 2550 x 3300 letter pages (16
+    distinct, replicated), one call per operation, as the benchmark times
+    it.  The 16 distinct pages are checked whole against the oracle's
+    summed-area evaluator, every replica's row counts against its original;
+    the packed and run-length transposes of the batch are checked by
+    transposing back."""
+    B, D = 256, 16
+    pool = [pagegen.letter_page(2000 + i) for i in range(D)]
+    W, H = 2550, 3300
+    host = np.concatenate([pool[i % D].words() for i in range(B)])
+    src = M.Bitmap.from_words(host, W, npages=B)
+    del host
+    r_in = M.pack_to_rle(src)
+    se = (21, 21, 10, 10) if op in ("erode", "open") else (1, 31, 0, 15)
+    out = M.rect_rlet(op, r_in, se)
+    back = M.rle_to_pack(out).to_numpy().reshape(B, H, -1)
+    torch.cuda.synchronize()
+    for i in range(D):
+        want = oracle.pack(oracle.sat_apply(op, pool[i].img, se))
+        np.testing.assert_array_equal(back[i], want, err_msg="%s %s page %d" % (op, se, i))
+    counts = np.diff(out.row_ptr.cpu().numpy()).reshape(B, H)
+    for i in range(D, B):
+        np.testing.assert_array_equal(counts[i], counts[i % D], err_msg="replica %d" % i)
+    del back, out
+    if op == "erode":
+        t = M.transpose_packed(src)
+        tb = M.transpose_packed(t)
+        torch.cuda.synchronize()
+        assert torch.equal(tb.words, M.rle_to_pack(r_in).words)
+        np.testing.assert_array_equal(t.to_numpy()[:W], oracle.pack(np.ascontiguousarray(pool[0].img.T)))
+        del t, tb
+        rt = M.transpose_rle(r_in)
+        rb = M.transpose_rle(rt)
+        torch.cuda.synchronize()
+        assert torch.equal(rb.row_ptr, r_in.row_ptr)
+        n = int(r_in.row_ptr[-1].item())
+        assert torch.equal(rb.runs[:n], r_in.runs[:n])
