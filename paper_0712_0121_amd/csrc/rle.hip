@@ -335,7 +335,7 @@ __global__ __launch_bounds__(64 * kDecodeWaves) void decode_transpose_kernel(
                 }
                 if (a >= x1) break;         // starts in a later word
                 const int lo = max(a, x0) - x0, hi = min(b, x1) - x0;
-                if (lo < hi) v |= ((hi == 64) ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+                if (lo < hi) v |= (~0ull >> (64 - (hi - lo))) << lo;   // bits lo .. hi - 1
                 if (b > x1) break;          // reaches into the next word
                 have = false;
             }
