@@ -522,3 +522,101 @@ def test_transpose_composition_matches_oracle(op):
         grp, gruns = otr.rlet_apply(op, rp, runs, W, se)
         np.testing.assert_array_equal(oracle.rle_decode(grp, gruns, W, H), oracle.apply(op, img, se),
                                       err_msg="%s %s %dx%d" % (op, se, H, W))
+
+
+# ------------------------------------------------ components and statistics
+from oracle import components as occ  # noqa: E402
+
+
+def _lines(img):
+    return otr.to_lines(*oracle.rle_encode(img))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_labels_match_scipy(conn):
+    st = ndi.generate_binary_structure(2, 1 if conn == 4 else 2)
+    for k in range(8):
+        r = np.random.default_rng(300 + k)
+        H, W = int(r.integers(1, 40)), int(r.integers(1, 60))
+        img = rnd_img(400 + k, H, W, float(r.choice([0.2, 0.45, 0.6])))
+        lines = _lines(img)
+        labels, n = occ.label_runs(lines, conn)
+        want, nw = ndi.label(img, structure=st)
+        assert n == nw
+        # scipy numbers components in raster order of their first pixel, as the oracle does
+        np.testing.assert_array_equal(occ.label_image(lines, labels, W), want)
+
+
+def test_connectivity_hand_example():
+    """Two diagonal pixels are one component under 8-connectivity and two
+    under 4; a U shape is one component either way."""
+    img = np.array([[1, 0, 0, 1, 0, 1],
+                    [0, 1, 0, 1, 0, 1],
+                    [0, 0, 0, 1, 1, 1]], dtype=np.uint8)
+    lines = _lines(img)
+    assert occ.label_runs(lines, 8)[1] == 2
+    assert occ.label_runs(lines, 4)[1] == 3
+    labels, _ = occ.label_runs(lines, 4)
+    assert labels == [[0, 1, 1], [2, 1, 1], [1]]
+
+
+def test_component_stats_match_scipy():
+    img = rnd_img(5, 37, 53, 0.4)
+    lines = _lines(img)
+    labels, n = occ.label_runs(lines, 8)
+    st = occ.component_stats(lines, labels, n)
+    lab, nw = ndi.label(img, structure=np.ones((3, 3)))
+    assert n == nw
+    for c, sl in enumerate(ndi.find_objects(lab)):
+        ys, xs = np.nonzero(lab == c + 1)
+        assert list(st[c, :4]) == [sl[1].start, sl[0].start, sl[1].stop, sl[0].stop]
+        assert st[c, 4] == len(xs) and st[c, 5] == xs.sum() and st[c, 6] == ys.sum()
+
+
+def test_run_histograms_brute_force():
+    img = rnd_img(9, 30, 70, 0.5)
+    img[3] = 0
+    img[4] = 1
+    black, white = occ.run_histograms(_lines(img), 70)
+    wb, ww = np.zeros(71, np.int64), np.zeros(71, np.int64)
+    for row in img:
+        s = "".join(map(str, row))
+        for m in __import__("re").finditer("1+", s):
+            wb[len(m.group())] += 1
+        for m in __import__("re").finditer("(?<=1)0+(?=1)", s):
+            ww[len(m.group())] += 1
+    np.testing.assert_array_equal(black, wb)
+    np.testing.assert_array_equal(white, ww)
+    assert black.sum() == oracle.rle_encode(img)[0][-1]
+
+
+def test_histogram_percentile_against_sorted_lengths():
+    r = np.random.default_rng(3)
+    for _ in range(20):
+        h = r.integers(0, 5, 40)
+        lengths = np.repeat(np.arange(40), h)
+        for num, den in [(1, 2), (9, 10), (1, 1), (1, 100)]:
+            if len(lengths) == 0:
+                assert occ.histogram_percentile(h, num, den) == 0
+                continue
+            k = -(-len(lengths) * num // den)          # ceil: the k-th smallest length
+            assert occ.histogram_percentile(h, num, den) == np.sort(lengths)[k - 1]
+
+
+def test_layout_boxes_two_blocks():
+    """Two text blocks of 'words' (3 x 2 rectangles two pixels apart, rows of
+    words five rows apart) far from each other: with the 90th percentile the
+    gaps inside the blocks close and each block is one box."""
+    W, H = 120, 60
+    img = np.zeros((H, W), np.uint8)
+    for (x0, y0) in [(5, 5), (70, 30)]:
+        for row in range(3):
+            for word in range(5):
+                x, y = x0 + 5 * word, y0 + 5 * row
+                img[y:y + 2, x:x + 3] = 1
+    gx, gy, st = occ.layout_boxes([_lines(img)], W, 9, 10)
+    assert gx == 2 and gy == 3
+    boxes = sorted(tuple(b[:4]) for b in st[0])
+    # dilating by 3 x 4 with origin (1, 2) covers [x - 1, x + 1] x [y - 1, y + 2] around each
+    # pixel: a block [5, 28) x [5, 17) becomes [4, 29) x [3, 18)
+    assert boxes == [(4, 3, 29, 18), (69, 28, 94, 43)]
