@@ -210,6 +210,51 @@ int morph_rect_rlet(int op, const morph_rle_t *dst, const morph_rle_t *src, morp
                     size_t ws_bytes, morph_stream_t stream);
 size_t morph_rlet_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se);
 
+/* ---- components and statistics (sections "Connected Component Extraction
+ *      and Statistics", "Other Operations") ----------------------------------- */
+/*
+ * Connected components of the runs of every page.  Two runs of neighbouring
+ * rows touch when their pixel intervals overlap (connectivity 4) or overlap
+ * after widening by one pixel (connectivity 8).  labels[i] receives the
+ * component number of run i (runs counted over all pages, as in row_ptr),
+ * numbered 0, 1, ... within each page in the raster order of each
+ * component's first run.  comp_ptr (npages + 1 int32, device) receives the
+ * index of each page's first component in a numbering over all pages;
+ * comp_ptr[npages] is the total.  labels must hold max_runs int32; runs with
+ * index >= max_runs are not labelled and comp_ptr[npages] is set to -1 (check
+ * after the stream has passed the call; passing src->capacity is always
+ * enough).  ws: 256-byte aligned, morph_rle_label_workspace_bytes(height *
+ * npages, max_runs) bytes.  The union-find links are made with atomics, but
+ * the labels do not depend on their order.
+ */
+int morph_rle_label(const morph_rle_t *src, int32_t connectivity, int32_t *labels, int64_t max_runs,
+                    int32_t *comp_ptr, void *ws, size_t ws_bytes, morph_stream_t stream);
+size_t morph_rle_label_workspace_bytes(int32_t rows, int64_t max_runs);
+
+/* Statistics of one component: bounding box [x0, x1) x [y0, y1) in page
+ * coordinates, pixel count and the sums of the pixels' x and y (centroid =
+ * sum / area). */
+typedef struct {
+    int32_t x0, y0, x1, y1;
+    int64_t area, sum_x, sum_y;
+} morph_component_t;
+/* Statistics of the components morph_rle_label found (labels, comp_ptr and
+ * max_runs as given to it): stats[c] for component c of the numbering over
+ * all pages, c < max_components (components past that are skipped). */
+int morph_rle_component_stats(const morph_rle_t *src, const int32_t *labels, int64_t max_runs,
+                              const int32_t *comp_ptr, morph_component_t *stats, int64_t max_components,
+                              morph_stream_t stream);
+/* Run-length histograms per page: black[p * (width + 1) + n] = black runs of
+ * length n on page p, white[...] = white runs of length n lying between two
+ * black runs of the same row.  Each array: npages * (width + 1) int32,
+ * overwritten.  Vertical histograms: transpose first (morph_transpose_rle). */
+int morph_rle_run_histograms(const morph_rle_t *src, int32_t *black, int32_t *white, morph_stream_t stream);
+/* out[0] = the smallest n at which the running count of the summed
+ * histograms hist[p * nbins + n] (p < nrows) reaches num/den of their total
+ * (0 for empty histograms); 0 < num <= den <= 2^20. */
+int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins, int32_t num, int32_t den,
+                               int32_t *out, morph_stream_t stream);
+
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
  * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
@@ -297,7 +342,10 @@ enum {
     MORPH_K_TRANSPOSE = 7,     /* packed bitmap -> its transpose */
     MORPH_K_DECODE_T = 8,      /* runs -> transposed packed bitmap, with a within-line
                                   operation applied to the runs as they are read */
-    MORPH_K_COUNT = 9
+    MORPH_K_COMPONENTS = 9,    /* connected-component labelling of runs (all its launches) */
+    MORPH_K_COMPONENT_STATS = 10, /* per-component box, area and coordinate sums */
+    MORPH_K_HISTOGRAM = 11,    /* run-length histograms */
+    MORPH_K_COUNT = 12
 };
 typedef struct {
     int64_t launches;

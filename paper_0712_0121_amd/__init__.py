@@ -37,7 +37,10 @@ __all__ = [
     "morph_batch_launch", "Trace",
     "morph_transpose_packed", "morph_transpose_rle", "morph_transpose_rle_workspace_bytes",
     "morph_rect_rlet", "morph_rlet_workspace_bytes",
+    "morph_rle_label", "morph_rle_label_workspace_bytes", "morph_rle_component_stats", "morph_component_t",
+    "morph_rle_run_histograms", "morph_histogram_percentile",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack", "transpose_packed", "transpose_rle", "rect_rlet",
+    "label_components", "component_stats", "run_histograms", "histogram_percentile", "layout_boxes",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmorph.so")
@@ -67,11 +70,16 @@ class morph_se_t(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32)]
 
 
+class morph_component_t(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("x1", ctypes.c_int32), ("y1", ctypes.c_int32),
+                ("area", ctypes.c_int64), ("sum_x", ctypes.c_int64), ("sum_y", ctypes.c_int64)]
+
+
 class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 9
+MORPH_K_COUNT = 12
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -111,6 +119,11 @@ def _load():
         "morph_transpose_rle_workspace_bytes": (SZ, [I32, I32, I32]),
         "morph_rect_rlet": (ctypes.c_int, [ctypes.c_int, RL, RL, SE, P, SZ, P]),
         "morph_rlet_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
+        "morph_rle_label": (ctypes.c_int, [RL, I32, P, I64, P, P, SZ, P]),
+        "morph_rle_label_workspace_bytes": (SZ, [I32, I64]),
+        "morph_rle_component_stats": (ctypes.c_int, [RL, P, I64, P, P, I64, P]),
+        "morph_rle_run_histograms": (ctypes.c_int, [RL, P, P, P]),
+        "morph_histogram_percentile": (ctypes.c_int, [P, I32, I32, I32, I32, P, P]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -368,6 +381,39 @@ def morph_rect_rlet(op, dst: RLE, src: RLE, s, ws=None, stream=None):
            "morph_rect_rlet")
 
 
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def morph_rle_label_workspace_bytes(rows, max_runs) -> int:
+    return int(_lib.morph_rle_label_workspace_bytes(int(rows), int(max_runs)))
+
+
+def morph_rle_label(src: RLE, connectivity, labels, max_runs, comp_ptr, ws=None, stream=None):
+    r = src.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_rle_label(ctypes.byref(r), int(connectivity), _ptr(labels), int(max_runs), _ptr(comp_ptr),
+                                p, n, _stream(stream)), "morph_rle_label")
+
+
+def morph_rle_component_stats(src: RLE, labels, max_runs, comp_ptr, stats, max_components, stream=None):
+    r = src.struct()
+    _check(_lib.morph_rle_component_stats(ctypes.byref(r), _ptr(labels), int(max_runs), _ptr(comp_ptr),
+                                          _ptr(stats), int(max_components), _stream(stream)),
+           "morph_rle_component_stats")
+
+
+def morph_rle_run_histograms(src: RLE, black, white, stream=None):
+    r = src.struct()
+    _check(_lib.morph_rle_run_histograms(ctypes.byref(r), _ptr(black), _ptr(white), _stream(stream)),
+           "morph_rle_run_histograms")
+
+
+def morph_histogram_percentile(hist, nrows, nbins, num, den, out, stream=None):
+    _check(_lib.morph_histogram_percentile(_ptr(hist), int(nrows), int(nbins), int(num), int(den), _ptr(out),
+                                           _stream(stream)), "morph_histogram_percentile")
+
+
 class BatchPlan:
     """Many packed pages, each with its own operation and element, run as one
     persistent launch (morph_batch_plan_create / morph_batch_run)."""
@@ -533,3 +579,64 @@ def rect_rlet(op: str, src: RLE, s, dst: RLE | None = None, stream=None) -> RLE:
     ws = _alloc_ws(morph_rlet_workspace_bytes(op, src.width, src.height, src.npages, s), src.row_ptr.device)
     morph_rect_rlet(op, dst, src, s, ws, stream)
     return dst
+
+
+def label_components(src: RLE, connectivity: int = 8, stream=None):
+    """Component number of every run (int32, one per run, numbered per page)
+    and comp_ptr (int32, npages + 1).  Reads the run count first (a
+    synchronisation) to size the label array."""
+    dev = src.row_ptr.device
+    n = src.nruns()
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    comp_ptr = torch.empty(src.npages + 1, dtype=torch.int32, device=dev)
+    ws = _alloc_ws(morph_rle_label_workspace_bytes(src.height * src.npages, n), dev)
+    morph_rle_label(src, connectivity, labels, n, comp_ptr, ws, stream)
+    return labels[:n], comp_ptr
+
+
+def component_stats(src: RLE, labels, comp_ptr, stream=None):
+    """Per component over all pages: (boxes int32 (n, 4) as x0, y0, x1, y1;
+    sums int64 (n, 3) as area, sum_x, sum_y).  Reads the component count
+    first (a synchronisation)."""
+    total = int(comp_ptr[-1].item())
+    if total < 0:
+        raise MorphError(-6, "component_stats: labelling ran out of room")
+    raw = torch.empty((max(total, 1), 10), dtype=torch.int32, device=labels.device)
+    morph_rle_component_stats(src, labels, labels.numel(), comp_ptr, raw, total, stream)
+    return raw[:total, :4], raw[:total, 4:].contiguous().view(torch.int64)
+
+
+def run_histograms(src: RLE, stream=None):
+    """(black, white) int32 histograms, shape (npages, width + 1)."""
+    dev = src.row_ptr.device
+    black = torch.empty((src.npages, src.width + 1), dtype=torch.int32, device=dev)
+    white = torch.empty_like(black)
+    morph_rle_run_histograms(src, black, white, stream)
+    return black, white
+
+
+def histogram_percentile(hist, num: int, den: int, stream=None):
+    """Device int32 tensor [1]: the percentile num/den of the summed rows of hist."""
+    out = torch.empty(1, dtype=torch.int32, device=hist.device)
+    morph_histogram_percentile(hist, hist.shape[0], hist.shape[1], num, den, out, stream)
+    return out
+
+
+def layout_boxes(src: RLE, num: int = 1, den: int = 3, connectivity: int = 8, stream=None):
+    """Layout analysis on runs: gx, gy = percentile num/den of the horizontal
+    and vertical (by transposition) white runs between black ones over the
+    whole stack; the pages dilated by the centred (gx + 1) x (gy + 1)
+    rectangle; the connected components of the result and their boxes.
+    Returns (gx, gy, boxes, sums, comp_ptr); the element is read back to
+    the host (a synchronisation) because it sets the launch."""
+    _, hw = run_histograms(src, stream)
+    t = transpose_rle(src, stream)
+    _, vw = run_histograms(t, stream)
+    g = torch.cat([histogram_percentile(hw, num, den, stream), histogram_percentile(vw, num, den, stream)])
+    gx, gy = (int(v) for v in g.tolist())
+    del t
+    s = (gx + 1, gy + 1, (gx + 1) // 2, (gy + 1) // 2)
+    smeared = rect_rle("dilate", src, s, stream=stream)
+    labels, comp_ptr = label_components(smeared, connectivity, stream)
+    boxes, sums = component_stats(smeared, labels, comp_ptr, stream)
+    return gx, gy, boxes, sums, comp_ptr

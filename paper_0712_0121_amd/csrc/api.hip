@@ -750,6 +750,72 @@ int morph_rect_rlet(int op, const morph_rle_t *dst, const morph_rle_t *src, morp
     return rlet_run(op, *dst, *src, se, (char *)ws, L, (hipStream_t)stream);
 }
 
+size_t morph_rle_label_workspace_bytes(int32_t rows, int64_t max_runs)
+{
+    if (rows < 1 || max_runs < 0 || max_runs >= 0x7fffffffLL) return 0;
+    return cc_workspace(rows, max_runs);
+}
+
+int morph_rle_label(const morph_rle_t *src, int32_t connectivity, int32_t *labels, int64_t max_runs,
+                    int32_t *comp_ptr, void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    if (!rle_ok(src) || (connectivity != 4 && connectivity != 8) || !comp_ptr || max_runs < 0 ||
+        (max_runs > 0 && !labels) || (((uintptr_t)labels) & 3) || (((uintptr_t)comp_ptr) & 3))
+        return MORPH_E_INVAL;
+    if (max_runs >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    const long long R = (long long)src->height * src->npages;
+    const size_t need = cc_workspace(R, max_runs);
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < need) return MORPH_E_WORKSPACE;
+    const size_t lb = (size_t)max_runs * 4, cb = ((size_t)src->npages + 1) * 4;
+    if ((lb && (overlap(labels, lb, src->runs, rle_extent_runs(src)) ||
+                overlap(labels, lb, src->row_ptr, rle_extent_rp(src)) || overlap(labels, lb, comp_ptr, cb))) ||
+        overlap(comp_ptr, cb, src->row_ptr, rle_extent_rp(src)) ||
+        (src->capacity && overlap(comp_ptr, cb, src->runs, rle_extent_runs(src))))
+        return MORPH_E_ALIAS;
+    hipError_t e = cc_label(*src, connectivity, labels, max_runs, comp_ptr, ws, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_rle_component_stats(const morph_rle_t *src, const int32_t *labels, int64_t max_runs,
+                              const int32_t *comp_ptr, morph_component_t *stats, int64_t max_components,
+                              morph_stream_t stream)
+{
+    if (!rle_ok(src) || !comp_ptr || max_runs < 0 || max_components < 0 || (max_runs > 0 && !labels) ||
+        (max_components > 0 && !stats) || (((uintptr_t)stats) & 7))
+        return MORPH_E_INVAL;
+    if (max_runs >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    hipError_t e = cc_stats(*src, labels, max_runs, comp_ptr, stats, max_components, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_rle_run_histograms(const morph_rle_t *src, int32_t *black, int32_t *white, morph_stream_t stream)
+{
+    if (!rle_ok(src) || !black || !white || (((uintptr_t)black) & 3) || (((uintptr_t)white) & 3))
+        return MORPH_E_INVAL;
+    const size_t hb = (size_t)src->npages * ((size_t)src->width + 1) * 4;
+    if (overlap(black, hb, white, hb) || overlap(black, hb, src->row_ptr, rle_extent_rp(src)) ||
+        overlap(white, hb, src->row_ptr, rle_extent_rp(src)) ||
+        (src->capacity && (overlap(black, hb, src->runs, rle_extent_runs(src)) ||
+                           overlap(white, hb, src->runs, rle_extent_runs(src)))))
+        return MORPH_E_ALIAS;
+    hipError_t e = run_histograms(*src, black, white, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins, int32_t num, int32_t den,
+                               int32_t *out, morph_stream_t stream)
+{
+    if (!hist || !out || nrows < 1 || nbins < 1 || num < 1 || den < num || den > (1 << 20) ||
+        (((uintptr_t)hist) & 3) || (((uintptr_t)out) & 3))
+        return MORPH_E_INVAL;
+    hipError_t e = histogram_percentile(hist, nrows, nbins, num, den, out, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
 {
     if (!rle_ok(r)) return MORPH_E_INVAL;
@@ -837,7 +903,8 @@ const char *morph_kernel_name(int k)
     static const char *names[MORPH_K_COUNT] = {"rect_kernel", "rect_batch_kernel", "pack_to_rle_kernel",
                                                "rle_to_pack_kernel", "row_erode_kernel", "col_and_kernel",
                                                "pack_rows_kernel", "transpose_kernel",
-                                               "decode_transpose_kernel"};
+                                               "decode_transpose_kernel", "components",
+                                               "component_stats_kernel", "run_hist_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

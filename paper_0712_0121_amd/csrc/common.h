@@ -132,6 +132,20 @@ size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t s
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 size_t scan_workspace(int64_t n);
+// out[0..n] = exclusive scan of in[0..n-1], out[n] = total; tmp holds
+// scan_workspace(n) bytes.
+hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipStream_t s);
+
+// Connected components of a run-length image (runs with index >= nmax are
+// left out; comp_ptr[npages] is then -1), their statistics, and run-length
+// histograms.
+size_t cc_workspace(long long rows, long long nruns);
+hipError_t cc_label(const morph_rle_t &src, int connectivity, int *labels, long long nmax, int *comp_ptr,
+                    void *ws, hipStream_t s);
+hipError_t cc_stats(const morph_rle_t &src, const int *labels, long long nmax, const int *comp_ptr,
+                    morph_component_t *st, long long ncap, hipStream_t s);
+hipError_t run_histograms(const morph_rle_t &src, int *black, int *white, hipStream_t s);
+hipError_t histogram_percentile(const int *hist, int nrows, int nbins, int num, int den, int *out, hipStream_t s);
 
 // Within-line operation applied to every run (or, with comp, every gap) of
 // a row as it is decoded: erosion shrinks an interval, dilation grows it,

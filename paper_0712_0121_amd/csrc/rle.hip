@@ -938,7 +938,7 @@ unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / pe
 size_t scan_workspace(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock + 1) * sizeof(int); }
 
 // out[0..n] = exclusive scan of in[0..n-1], out[n] = total.
-static hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipStream_t s)
+hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipStream_t s)
 {
     if (n == 0) {
         hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, s, out);

@@ -209,3 +209,36 @@ def test_rlet_argument_errors(op):
     huge_a = M.morph_rle_t(100000, 60000, 1, 1 << 40, (1 << 40) + (1 << 30), 10**10)
     huge_b = M.morph_rle_t(100000, 60000, 1, 2 << 40, (2 << 40) + (1 << 30), 10**10)
     assert call(huge_a, huge_b) == -8
+
+
+def test_component_argument_errors():
+    a, b, c = HostBuf(1 << 16), HostBuf(1 << 16), HostBuf(1 << 16)
+    W, H = 100, 20
+    src = rle(a, W, H, 500)
+    lab, cp = b.ptr, c.ptr
+    need = M.morph_rle_label_workspace_bytes(H, 500)
+    assert need >= 500 * 4 + H * 4
+    L = lambda s, conn=8, labels=lab, n=500, comp=cp, ws=None, nb=0: M._lib.morph_rle_label(
+        ctypes.byref(s), conn, labels, n, comp, ws, nb, None)
+    assert L(src, conn=6) == -1
+    assert L(src, comp=None) == -1
+    assert L(src, n=-1) == -1
+    assert L(src, labels=lab + 2) == -1                        # misaligned
+    assert L(src) == -4
+    ws = HostBuf(need + 512)
+    al = (ws.ptr + 255) & ~255
+    assert L(src, ws=al, nb=need - 1) == -4
+    assert L(src, labels=a.ptr + 8, ws=al, nb=need) == -3      # labels over the row counts
+    assert L(src, n=1 << 31, ws=al, nb=need) == -8
+    S = lambda st, ncap: M._lib.morph_rle_component_stats(ctypes.byref(src), lab, 500, cp, st, ncap, None)
+    assert S(None, 5) == -1
+    assert S(c.ptr + 4, 5) == -1
+    Hh = lambda bl, wh: M._lib.morph_rle_run_histograms(ctypes.byref(src), bl, wh, None)
+    assert Hh(None, c.ptr) == -1
+    assert Hh(b.ptr, b.ptr + 16) == -3
+    P = lambda h, rows, bins, num, den, out: M._lib.morph_histogram_percentile(h, rows, bins, num, den, out, None)
+    assert P(b.ptr, 1, 10, 0, 10, c.ptr) == -1
+    assert P(b.ptr, 1, 10, 11, 10, c.ptr) == -1
+    assert P(b.ptr, 1, 10, 1, (1 << 20) + 1, c.ptr) == -1
+    assert P(b.ptr, 0, 10, 1, 2, c.ptr) == -1
+    assert ctypes.sizeof(M.morph_component_t) == 40
