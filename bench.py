@@ -13,7 +13,10 @@ It prints one JSON line: Gpixel/s over the step (pixels counted once per
 operation and path), the roofline of the dominant kernel measured with HIP
 events inside the timed region, and the CPU oracle timed on a sample of the
 same work.  Pages are synthetic (seeded), standing in for scanned 300 dpi
-letter pages.
+letter pages.  Extras beside the step (outside `value`): the mixed batch in
+one persistent launch, the representation choice, the serving loop,
+transposition and the transpose-based operations, and connected components
+with the layout composition.
 """
 from __future__ import annotations
 
@@ -42,9 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
-    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose"], default="all",
-                    help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose' "
-                         "prints only the transposition measurements")
+    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose", "components"], default="all",
+                    help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose' and "
+                         "'components' print only those measurements")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -298,6 +301,60 @@ def bench_transpose(M, dev, src, rle_ms_per_op):
     return out
 
 
+def bench_components(M, dev, src):
+    """Connected components (8-connectivity), component statistics and
+    run-length histograms of the letter batch on runs, and the layout
+    composition (spacing estimate, dilation, components, boxes) end to end.
+    Algorithmic bytes: labelling reads 8 B per run and 4 B per row count and
+    writes 4 B per label; statistics read 8 + 4 B per run and write 40 B per
+    component; histograms read 8 B per run."""
+    import torch
+    W, H, B = src.width, src.height, src.npages
+    r = M.RLE.empty(W, H, B, device=dev)
+    ws_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * B), dtype=torch.uint8, device=dev)
+    M.morph_pack_to_rle(r, src, ws_p2r)
+    del ws_p2r
+    n = r.nruns()
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    comp_ptr = torch.empty(B + 1, dtype=torch.int32, device=dev)
+    ws = torch.empty(M.morph_rle_label_workspace_bytes(H * B, n), dtype=torch.uint8, device=dev)
+    t_lab = time_ms(lambda: M.morph_rle_label(r, 8, labels, n, comp_ptr, ws), 5)
+    nc = int(comp_ptr[-1].item())
+    st = torch.empty((max(nc, 1), 10), dtype=torch.int32, device=dev)
+    t_st = time_ms(lambda: M.morph_rle_component_stats(r, labels, n, comp_ptr, st, nc), 5)
+    bl = torch.empty((B, W + 1), dtype=torch.int32, device=dev)
+    wh = torch.empty_like(bl)
+    t_h = time_ms(lambda: M.morph_rle_run_histograms(r, bl, wh), 5)
+    del ws, st, bl, wh
+    torch.cuda.empty_cache()
+    M.layout_boxes(r)                           # warm-up (allocations)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gx, gy, boxes, sums, cp = M.layout_boxes(r)
+    torch.cuda.synchronize()
+    t_lay = (time.perf_counter() - t0) * 1e3 / reps
+    with M.Trace() as tr:
+        M.layout_boxes(r)
+    px = W * H * B
+    gbs = lambda b, ms: b / (ms / 1e3) / 1e9
+    b_lab = 12.0 * n + 4.0 * (H * B + 1)
+    b_st = 12.0 * n + 40.0 * nc
+    out = {"pages": B, "runs": n, "components": nc,
+           "label": {"ms": t_lab, "gpixel_s": px / (t_lab / 1e3) / 1e9, "alg_bytes": b_lab,
+                     "gbs": gbs(b_lab, t_lab), "hbm_frac": gbs(b_lab, t_lab) / HBM_PEAK_GBS},
+           "stats": {"ms": t_st, "alg_bytes": b_st, "gbs": gbs(b_st, t_st)},
+           "histograms": {"ms": t_h, "gbs": gbs(8.0 * n, t_h)},
+           "layout": {"ms_wall": t_lay, "pages_s": B / (t_lay / 1e3), "gx": gx, "gy": gy,
+                      "blocks": int(cp[-1].item()),
+                      "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4)}
+                                  for k, v in tr.result.items()}}}
+    del r, labels, comp_ptr
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_repr(M, dev, tuner):
     """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
     (conversions included), as the autotuner records it."""
@@ -328,14 +385,14 @@ def main():
     words_pool = [torch.from_numpy(p.words().view(np.int64)) for p in pool]
     host = torch.cat([words_pool[i % len(pool)] for i in range(B)], dim=0)
     src = M.Bitmap(host.to(dev), W, H, B)
-    if args.only == "transpose":
+    if args.only in ("transpose", "components"):
         del host
-        res = bench_transpose(M, dev, src, None)
+        res = bench_transpose(M, dev, src, None) if args.only == "transpose" else bench_components(M, dev, src)
         # the elementwise copy whose HBM counters calibrate the profiles
         cal = torch.empty_like(src.words)
         torch.bitwise_or(src.words, 0, out=cal)
         torch.cuda.synchronize()
-        print(json.dumps({"transpose": res}), flush=True)
+        print(json.dumps({args.only: res}), flush=True)
         return
     dst = M.Bitmap.empty(W, H, B, device=dev)
     back = M.Bitmap.empty(W, H, B, device=dev)
@@ -520,6 +577,7 @@ def main():
         out["repr_choice"] = bench_repr(M, dev, tuner)
         out["serving"] = bench_serving(M, dev, args.serve_seconds)
         out["transpose"] = bench_transpose(M, dev, src, breakdown.get("rle", {}).get("ms_per_op"))
+        out["components"] = bench_components(M, dev, src)
         try:
             tuner.save()
         except OSError:

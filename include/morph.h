@@ -251,9 +251,12 @@ int morph_rle_component_stats(const morph_rle_t *src, const int32_t *labels, int
 int morph_rle_run_histograms(const morph_rle_t *src, int32_t *black, int32_t *white, morph_stream_t stream);
 /* out[0] = the smallest n at which the running count of the summed
  * histograms hist[p * nbins + n] (p < nrows) reaches num/den of their total
- * (0 for empty histograms); 0 < num <= den <= 2^20. */
+ * (0 for empty histograms); 0 < num <= den <= 2^20; the total must stay
+ * below 2^31.  ws: 256-byte aligned, morph_histogram_percentile_workspace_bytes(nbins)
+ * bytes (the summed histogram). */
 int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins, int32_t num, int32_t den,
-                               int32_t *out, morph_stream_t stream);
+                               int32_t *out, void *ws, size_t ws_bytes, morph_stream_t stream);
+size_t morph_histogram_percentile_workspace_bytes(int32_t nbins);
 
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..

@@ -38,7 +38,7 @@ __all__ = [
     "morph_transpose_packed", "morph_transpose_rle", "morph_transpose_rle_workspace_bytes",
     "morph_rect_rlet", "morph_rlet_workspace_bytes",
     "morph_rle_label", "morph_rle_label_workspace_bytes", "morph_rle_component_stats", "morph_component_t",
-    "morph_rle_run_histograms", "morph_histogram_percentile",
+    "morph_rle_run_histograms", "morph_histogram_percentile", "morph_histogram_percentile_workspace_bytes",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack", "transpose_packed", "transpose_rle", "rect_rlet",
     "label_components", "component_stats", "run_histograms", "histogram_percentile", "layout_boxes",
 ]
@@ -123,7 +123,8 @@ def _load():
         "morph_rle_label_workspace_bytes": (SZ, [I32, I64]),
         "morph_rle_component_stats": (ctypes.c_int, [RL, P, I64, P, P, I64, P]),
         "morph_rle_run_histograms": (ctypes.c_int, [RL, P, P, P]),
-        "morph_histogram_percentile": (ctypes.c_int, [P, I32, I32, I32, I32, P, P]),
+        "morph_histogram_percentile": (ctypes.c_int, [P, I32, I32, I32, I32, P, P, SZ, P]),
+        "morph_histogram_percentile_workspace_bytes": (SZ, [I32]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -409,9 +410,14 @@ def morph_rle_run_histograms(src: RLE, black, white, stream=None):
            "morph_rle_run_histograms")
 
 
-def morph_histogram_percentile(hist, nrows, nbins, num, den, out, stream=None):
+def morph_histogram_percentile_workspace_bytes(nbins) -> int:
+    return int(_lib.morph_histogram_percentile_workspace_bytes(int(nbins)))
+
+
+def morph_histogram_percentile(hist, nrows, nbins, num, den, out, ws=None, stream=None):
+    p, n = _ws(ws)
     _check(_lib.morph_histogram_percentile(_ptr(hist), int(nrows), int(nbins), int(num), int(den), _ptr(out),
-                                           _stream(stream)), "morph_histogram_percentile")
+                                           p, n, _stream(stream)), "morph_histogram_percentile")
 
 
 class BatchPlan:
@@ -618,7 +624,8 @@ def run_histograms(src: RLE, stream=None):
 def histogram_percentile(hist, num: int, den: int, stream=None):
     """Device int32 tensor [1]: the percentile num/den of the summed rows of hist."""
     out = torch.empty(1, dtype=torch.int32, device=hist.device)
-    morph_histogram_percentile(hist, hist.shape[0], hist.shape[1], num, den, out, stream)
+    ws = _alloc_ws(morph_histogram_percentile_workspace_bytes(hist.shape[1]), hist.device)
+    morph_histogram_percentile(hist, hist.shape[0], hist.shape[1], num, den, out, ws, stream)
     return out
 
 

@@ -805,13 +805,22 @@ int morph_rle_run_histograms(const morph_rle_t *src, int32_t *black, int32_t *wh
     return MORPH_OK;
 }
 
+size_t morph_histogram_percentile_workspace_bytes(int32_t nbins)
+{
+    return nbins < 1 ? 0 : percentile_workspace(nbins);
+}
+
 int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins, int32_t num, int32_t den,
-                               int32_t *out, morph_stream_t stream)
+                               int32_t *out, void *ws, size_t ws_bytes, morph_stream_t stream)
 {
     if (!hist || !out || nrows < 1 || nbins < 1 || num < 1 || den < num || den > (1 << 20) ||
         (((uintptr_t)hist) & 3) || (((uintptr_t)out) & 3))
         return MORPH_E_INVAL;
-    hipError_t e = histogram_percentile(hist, nrows, nbins, num, den, out, (hipStream_t)stream);
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < percentile_workspace(nbins)) return MORPH_E_WORKSPACE;
+    const size_t hb = (size_t)nrows * nbins * 4;
+    if (overlap(ws, percentile_workspace(nbins), hist, hb) || overlap(ws, percentile_workspace(nbins), out, 4))
+        return MORPH_E_ALIAS;
+    hipError_t e = histogram_percentile(hist, nrows, nbins, num, den, out, ws, (hipStream_t)stream);
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
     return MORPH_OK;
 }

@@ -145,7 +145,9 @@ hipError_t cc_label(const morph_rle_t &src, int connectivity, int *labels, long 
 hipError_t cc_stats(const morph_rle_t &src, const int *labels, long long nmax, const int *comp_ptr,
                     morph_component_t *st, long long ncap, hipStream_t s);
 hipError_t run_histograms(const morph_rle_t &src, int *black, int *white, hipStream_t s);
-hipError_t histogram_percentile(const int *hist, int nrows, int nbins, int num, int den, int *out, hipStream_t s);
+size_t percentile_workspace(int nbins);
+hipError_t histogram_percentile(const int *hist, int nrows, int nbins, int num, int den, int *out, void *ws,
+                                hipStream_t s);
 
 // Within-line operation applied to every run (or, with comp, every gap) of
 // a row as it is decoded: erosion shrinks an interval, dilation grows it,

@@ -82,22 +82,92 @@ __device__ __forceinline__ void cc_unite(int *parent, int a, int b)
     }
 }
 
-__global__ __launch_bounds__(256) void cc_init_kernel(const int *__restrict__ rp, long long R, long long nmax,
-                                                      int *__restrict__ parent)
+// Union-find inside bands of kBandRows rows of a page, in LDS: the runs of
+// a band get local parents, the runs of each row are united with the
+// touching runs of the row above within the band, and every run's global
+// parent is set to the first run of its band-local set.  A band with more
+// runs than the LDS table holds does the same on the global parents (only
+// runs of its own band are touched, which its own threads initialised).
+// The rows that start a band are then joined to the row above by
+// cc_merge_kernel.
+constexpr int kBandRows = 32;
+constexpr int kBandRuns = 4096;
+
+__device__ __forceinline__ int lds_find(int *lp, int x)
 {
-    const long long r = (long long)xcd_block() * kCcGroupsPerBlock + (threadIdx.x >> 4);
-    if (r >= R) return;
-    int b0, b1;
-    cc_row(rp, r, nmax, b0, b1);
-    for (int i = b0 + cc_glane(); i < b1; i += kCcGroup) parent[i] = i;
+    int p = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (p != x) {
+        x = p;
+        p = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_unite(int *lp, int a, int b)
+{
+    for (;;) {
+        a = lds_find(lp, a);
+        b = lds_find(lp, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(lp + a, a, b) == a) return;
+    }
+}
+
+__global__ __launch_bounds__(256) void cc_band_kernel(const int *__restrict__ rp, const int2 *__restrict__ runs,
+                                                      int H, int bands_per_page, long long nbands, long long nmax,
+                                                      int widen, int *__restrict__ parent)
+{
+    __shared__ int lp[kBandRuns];
+    const long long band = xcd_block();
+    if (band >= nbands) return;             // whole workgroup
+    const long long page = band / bands_per_page;
+    const int y0 = (int)(band - page * bands_per_page) * kBandRows;
+    const long long r0 = page * H + y0, r1 = page * H + min(H, y0 + kBandRows);
+    const long long g0 = min((long long)max(rp[r0], 0), nmax);
+    const long long g1 = max(g0, min((long long)rp[r1], nmax));
+    const int n = (int)(g1 - g0);
+    const bool local = n <= kBandRuns;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        if (local) lp[k] = k; else parent[g0 + k] = (int)(g0 + k);
+    }
+    __syncthreads();
+    for (long long r = r0 + 1 + (threadIdx.x >> 4); r < r1; r += kCcGroupsPerBlock) {
+        int b0, b1, a0, a1;
+        cc_row(rp, r, nmax, b0, b1);
+        cc_row(rp, r - 1, nmax, a0, a1);
+        if (a0 == a1) continue;
+        for (int i = b0 + cc_glane(); i < b1; i += kCcGroup) {
+            const int2 q = runs[i];
+            int lo = a0, hi = a1;           // first run above whose end + widen passes s
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (runs[mid].y + widen > q.x) hi = mid; else lo = mid + 1;
+            }
+            for (int j = lo; j < a1; j++) {
+                if (runs[j].x >= q.y + widen) break;
+                if (local) lds_unite(lp, i - (int)g0, j - (int)g0); else cc_unite(parent, i, j);
+            }
+        }
+    }
+    __syncthreads();
+    if (local)
+        for (int k = threadIdx.x; k < n; k += 256) parent[g0 + k] = (int)(g0 + lds_find(lp, k));
 }
 
 __global__ __launch_bounds__(256) void cc_merge_kernel(const int *__restrict__ rp, const int2 *__restrict__ runs,
                                                        long long R, int H, long long nmax, int widen,
                                                        int *__restrict__ parent)
 {
-    const long long r = (long long)xcd_block() * kCcGroupsPerBlock + (threadIdx.x >> 4);
-    if (r >= R || r % H == 0) return;       // the first row of a page has nothing above
+    // rows that start a band (and not a page): b-th such row of the image
+    const long long b = (long long)xcd_block() * kCcGroupsPerBlock + (threadIdx.x >> 4);
+    const long long per_page = (H - 1) / kBandRows;          // band starts below row 0
+    if (per_page == 0 || b >= per_page * (R / H)) return;
+    const long long r = (b / per_page) * H + (b % per_page + 1) * kBandRows;
     int b0, b1, a0, a1;
     cc_row(rp, r, nmax, b0, b1);
     cc_row(rp, r - 1, nmax, a0, a1);
@@ -327,8 +397,23 @@ __global__ __launch_bounds__(256) void zero_ints_kernel(int *p, long long n)
     if (i < n) p[i] = 0;
 }
 
-// One workgroup: the histograms of all pages summed per bin, then the first
-// bin at which the running count reaches num/den of the total.
+// Sum of the histograms of all rows per bin: a grid over (bin chunk, row
+// chunk), each thread adding up to kSumRows rows of one bin.
+constexpr int kSumRows = 16;
+
+__global__ __launch_bounds__(256) void hist_sum_kernel(const int *__restrict__ hist, int nrows, int nbins,
+                                                       int *__restrict__ sum)
+{
+    const int b = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (b >= nbins) return;
+    const int p0 = (int)blockIdx.y * kSumRows, p1 = min(nrows, p0 + kSumRows);
+    int v = 0;
+    for (int p = p0; p < p1; p++) v += hist[(long long)p * nbins + b];
+    if (v) atomicAdd(sum + b, v);
+}
+
+// One workgroup over a single histogram (the sum over rows): its total,
+// then the first bin at which the running count reaches num/den of it.
 __global__ __launch_bounds__(256) void percentile_kernel(const int *__restrict__ hist, int nrows, int nbins,
                                                          long long num, long long den, int *out)
 {
@@ -405,9 +490,15 @@ hipError_t cc_label(const morph_rle_t &src, int connectivity, int *labels, long 
     const unsigned g = cc_blocks(R);
     const int2 *runs = reinterpret_cast<const int2 *>(src.runs);
     trace_before(MORPH_K_COMPONENTS, s);
-    hipLaunchKernelGGL(cc_init_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, nmax, parent);
-    hipLaunchKernelGGL(cc_merge_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, runs, R, src.height, nmax,
-                       connectivity == 8 ? 1 : 0, parent);
+    const int bpp = (src.height + kBandRows - 1) / kBandRows;
+    const long long nbands = (long long)bpp * src.npages;
+    const int widen = connectivity == 8 ? 1 : 0;
+    hipLaunchKernelGGL(cc_band_kernel, dim3((unsigned)nbands), dim3(256), 0, s, src.row_ptr, runs, src.height, bpp,
+                       nbands, nmax, widen, parent);
+    const long long starts = (long long)((src.height - 1) / kBandRows) * src.npages;
+    if (starts > 0)
+        hipLaunchKernelGGL(cc_merge_kernel, dim3(cc_blocks(starts)), dim3(256), 0, s, src.row_ptr, runs, R,
+                           src.height, nmax, widen, parent);
     hipLaunchKernelGGL(cc_flatten_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, nmax, parent, roots);
     hipError_t e = exclusive_scan(roots, (int)R, row_base, tmp, s);
     if (e != hipSuccess) return e;
@@ -450,9 +541,17 @@ hipError_t run_histograms(const morph_rle_t &src, int *black, int *white, hipStr
     return hipGetLastError();
 }
 
-hipError_t histogram_percentile(const int *hist, int nrows, int nbins, int num, int den, int *out, hipStream_t s)
+size_t percentile_workspace(int nbins) { return ((size_t)nbins * 4 + 255) & ~(size_t)255; }
+
+hipError_t histogram_percentile(const int *hist, int nrows, int nbins, int num, int den, int *out, void *ws,
+                                hipStream_t s)
 {
-    hipLaunchKernelGGL(percentile_kernel, dim3(1), dim3(256), 0, s, hist, nrows, nbins, (long long)num,
+    int *sum = (int *)ws;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, s, sum,
+                       (long long)nbins);
+    hipLaunchKernelGGL(hist_sum_kernel, dim3((unsigned)((nbins + 255) / 256), (unsigned)((nrows + kSumRows - 1) / kSumRows)),
+                       dim3(256), 0, s, hist, nrows, nbins, sum);
+    hipLaunchKernelGGL(percentile_kernel, dim3(1), dim3(256), 0, s, sum, 1, nbins, (long long)num,
                        (long long)den, out);
     return hipGetLastError();
 }

@@ -236,9 +236,16 @@ def test_component_argument_errors():
     Hh = lambda bl, wh: M._lib.morph_rle_run_histograms(ctypes.byref(src), bl, wh, None)
     assert Hh(None, c.ptr) == -1
     assert Hh(b.ptr, b.ptr + 16) == -3
-    P = lambda h, rows, bins, num, den, out: M._lib.morph_histogram_percentile(h, rows, bins, num, den, out, None)
+    P = lambda h, rows, bins, num, den, out, ws=None, nb=0: M._lib.morph_histogram_percentile(
+        h, rows, bins, num, den, out, ws, nb, None)
     assert P(b.ptr, 1, 10, 0, 10, c.ptr) == -1
     assert P(b.ptr, 1, 10, 11, 10, c.ptr) == -1
     assert P(b.ptr, 1, 10, 1, (1 << 20) + 1, c.ptr) == -1
     assert P(b.ptr, 0, 10, 1, 2, c.ptr) == -1
+    assert P(b.ptr, 1, 10, 1, 2, c.ptr) == -4
+    pw = M.morph_histogram_percentile_workspace_bytes(10)
+    assert pw >= 40
+    wsb = HostBuf(pw + 512)
+    wal = (wsb.ptr + 255) & ~255
+    assert P(b.ptr, 1, 10, 1, 2, c.ptr, wal, pw - 1) == -4
     assert ctypes.sizeof(M.morph_component_t) == 40
