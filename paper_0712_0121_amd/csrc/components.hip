@@ -7,10 +7,9 @@
 // intervals overlap, widened by one pixel for 8-connectivity).  The
 // union links the larger root under the smaller by compare-and-swap, so
 // the root of a component ends as its smallest run index: its first run in
-// raster order.  A flatten pass points every run at its root and counts the
-// roots per row; a scan of those counts numbers the components in raster
-// order, and every run takes its root's number less the number of
-// components on earlier pages.  All kernels give one 16-lane group to a
+// raster order.  The roots are counted per row; a scan of those counts
+// numbers the components of each page in raster order, and every run takes
+// its root's number.  All kernels give one 16-lane group to a
 // row and run through the row's runs in steps of 16.
 #include "common.h"
 
@@ -50,19 +49,6 @@ __device__ __forceinline__ int cc_find(int *parent, int x)
         if (gp != p) cc_store(parent + x, gp);
         x = p;
         p = gp;
-    }
-    return x;
-}
-
-// Root of x without writing: used once the links are final, while each
-// thread points its own run at its root (a halving store by another thread
-// could otherwise put an intermediate node back over that root).
-__device__ __forceinline__ int cc_find_ro(int *parent, int x)
-{
-    int p = cc_load(parent + x);
-    while (p != x) {
-        x = p;
-        p = cc_load(parent + x);
     }
     return x;
 }
@@ -186,28 +172,26 @@ __global__ __launch_bounds__(256) void cc_merge_kernel(const int *__restrict__ r
     }
 }
 
-// Points every run at its root and counts the roots of each row.
-__global__ __launch_bounds__(256) void cc_flatten_kernel(const int *__restrict__ rp, long long R, long long nmax,
-                                                         int *__restrict__ parent, int *__restrict__ roots)
+// Counts the roots of each row (the links are final: a root is a run that
+// is its own parent).
+__global__ __launch_bounds__(256) void cc_roots_kernel(const int *__restrict__ rp, long long R, long long nmax,
+                                                       const int *__restrict__ parent, int *__restrict__ roots)
 {
     const long long r = (long long)xcd_block() * kCcGroupsPerBlock + (threadIdx.x >> 4);
     const bool live = r < R;
     int b0 = 0, b1 = 0;
     if (live) cc_row(rp, r, nmax, b0, b1);
     int n = 0;
-    for (int i = b0 + cc_glane(); i < b1; i += kCcGroup) {
-        const int root = cc_find_ro(parent, i);
-        cc_store(parent + i, root);
-        n += (root == i);
-    }
+    for (int i = b0 + cc_glane(); i < b1; i += kCcGroup) n += (parent[i] == i);
     // sum over the group
     for (int d = kCcGroup / 2; d >= 1; d >>= 1) n += __shfl_xor(n, d, kCcGroup);
     if (live && cc_glane() == 0) roots[r] = n;
 }
 
-// Global number of every root: the roots before its row plus those before
-// it in the row.  Row 0 of each page records where the page's components
-// begin; the last row records the total.
+// Number of every root within its page: the roots before its row plus
+// those before it in the row, less the roots before the page's first row.
+// Row 0 of each page records where the page's components begin; the last
+// row records the total.
 __global__ __launch_bounds__(256) void cc_rank_kernel(const int *__restrict__ rp, long long R, int H, int P,
                                                       long long nmax, const int *__restrict__ parent,
                                                       const int *__restrict__ row_base, int *__restrict__ labels,
@@ -218,7 +202,7 @@ __global__ __launch_bounds__(256) void cc_rank_kernel(const int *__restrict__ rp
     int b0 = 0, b1 = 0;
     if (live) cc_row(rp, r, nmax, b0, b1);
     const int gl = cc_glane(), gbase = (int)(threadIdx.x & 63) & ~(kCcGroup - 1);
-    int base = live ? row_base[r] : 0;
+    int base = live ? row_base[r] - row_base[(r / H) * H] : 0;
     // every lane of the group takes the same number of steps (ballot below)
     for (int i0 = b0; i0 < b1; i0 += kCcGroup) {
         const int i = i0 + gl;
@@ -234,22 +218,20 @@ __global__ __launch_bounds__(256) void cc_rank_kernel(const int *__restrict__ rp
     }
 }
 
-// Pass 0: every run that is not a root takes its root's number less the
-// page's first; pass 1: the roots do the same (they are read in pass 0).
-__global__ __launch_bounds__(256) void cc_relabel_kernel(const int *__restrict__ rp, long long R, int H,
-                                                         long long nmax, const int *__restrict__ parent,
-                                                         const int *__restrict__ comp_ptr, int *__restrict__ labels,
-                                                         int pass)
+// Every run that is not a root takes its root's number (the links are
+// final, so the walk to the root only reads).
+__global__ __launch_bounds__(256) void cc_relabel_kernel(const int *__restrict__ rp, long long R, long long nmax,
+                                                         const int *__restrict__ parent, int *__restrict__ labels)
 {
     const long long r = (long long)xcd_block() * kCcGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= R) return;
     int b0, b1;
     cc_row(rp, r, nmax, b0, b1);
-    const int first = comp_ptr[r / H];
     for (int i = b0 + cc_glane(); i < b1; i += kCcGroup) {
-        const int root = parent[i];
-        if (pass == 0 && root != i) labels[i] = labels[root] - first;
-        if (pass == 1 && root == i) labels[i] -= first;
+        int root = parent[i];
+        if (root == i) continue;
+        for (int p = parent[root]; p != root; p = parent[root]) root = p;
+        labels[i] = labels[root];
     }
 }
 
@@ -499,15 +481,12 @@ hipError_t cc_label(const morph_rle_t &src, int connectivity, int *labels, long 
     if (starts > 0)
         hipLaunchKernelGGL(cc_merge_kernel, dim3(cc_blocks(starts)), dim3(256), 0, s, src.row_ptr, runs, R,
                            src.height, nmax, widen, parent);
-    hipLaunchKernelGGL(cc_flatten_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, nmax, parent, roots);
+    hipLaunchKernelGGL(cc_roots_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, nmax, parent, roots);
     hipError_t e = exclusive_scan(roots, (int)R, row_base, tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cc_rank_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, src.height, src.npages, nmax,
                        parent, row_base, labels, comp_ptr);
-    hipLaunchKernelGGL(cc_relabel_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, src.height, nmax, parent,
-                       comp_ptr, labels, 0);
-    hipLaunchKernelGGL(cc_relabel_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, src.height, nmax, parent,
-                       comp_ptr, labels, 1);
+    hipLaunchKernelGGL(cc_relabel_kernel, dim3(g), dim3(256), 0, s, src.row_ptr, R, nmax, parent, labels);
     trace_after(MORPH_K_COMPONENTS, s, 4.0 * (R + 1) + 4.0 * (src.npages + 1));
     return hipGetLastError();
 }
