@@ -620,3 +620,83 @@ def test_layout_boxes_two_blocks():
     # dilating by 3 x 4 with origin (1, 2) covers [x - 1, x + 1] x [y - 1, y + 2] around each
     # pixel: a block [5, 28) x [5, 17) becomes [4, 29) x [3, 18)
     assert boxes == [(4, 3, 29, 18), (69, 28, 94, 43)]
+
+
+# ----------------------------------------------------------- arbitrary masks
+from oracle import masks as omask  # noqa: E402
+
+
+def rnd_mask(seed, h, w, p=0.6):
+    r = np.random.default_rng(seed)
+    m = (r.random((h, w)) < p).astype(np.uint8)
+    return m, int(r.integers(0, w)), int(r.integers(0, h))
+
+
+@pytest.mark.parametrize("op", oracle.OPS)
+def test_mask_ops_match_scipy(op):
+    for k in range(10):
+        r = np.random.default_rng(500 + k)
+        img = rnd_img(600 + k, int(r.integers(1, 30)), int(r.integers(1, 40)), float(r.choice([0.3, 0.6, 0.85])))
+        m, cx, cy = rnd_mask(700 + k, int(r.integers(1, 7)), int(r.integers(1, 7)))
+        if not m.any():
+            m[cy, cx] = 1
+        h, w = m.shape
+        org = (cy - h // 2, cx - w // 2)
+        st = m.astype(bool)
+        ero = lambda a: ndi.binary_erosion(a, st, origin=org, border_value=1)
+        dil = lambda a: ndi.binary_dilation(a, st, origin=org, border_value=0)
+        a = img.astype(bool)
+        want = {"erode": lambda: ero(a), "dilate": lambda: dil(a),
+                "open": lambda: dil(ero(a)), "close": lambda: ero(dil(a))}[op]().astype(np.uint8)
+        np.testing.assert_array_equal(omask.apply(op, img, m, cx, cy), want, err_msg="%d %s" % (k, op))
+
+
+def test_full_mask_is_the_rectangle_and_disc_shape():
+    img = rnd_img(3, 25, 33, 0.6)
+    for se in [(3, 3, 1, 1), (5, 2, 0, 1), (1, 4, 0, 3)]:
+        w, h, cx, cy = se
+        for op in oracle.OPS:
+            np.testing.assert_array_equal(omask.apply(op, img, np.ones((h, w), np.uint8), cx, cy),
+                                          oracle.apply(op, img, se))
+    d, cx, cy = omask.disc(2)
+    assert d.tolist() == [[0, 0, 1, 0, 0], [0, 1, 1, 1, 0], [1, 1, 1, 1, 1], [0, 1, 1, 1, 0], [0, 0, 1, 0, 0]]
+    assert omask.runs_of(d, cx, cy) == [(0, -2, 1), (-1, -1, 3), (-2, 0, 5), (-1, 1, 3), (0, 2, 1)]
+
+
+def test_mask_hand_example():
+    """A plus sign (origin in its centre) on a 4 x 5 image, worked by hand:
+    a pixel survives erosion when it and its four neighbours are black
+    (outside counts black); dilation paints a plus around every black pixel."""
+    plus = np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]], np.uint8)
+    img = np.array([[1, 1, 1, 0, 0],
+                    [1, 1, 1, 0, 0],
+                    [0, 1, 1, 1, 0],
+                    [0, 0, 0, 0, 0]], np.uint8)
+    want_e = np.array([[1, 1, 0, 0, 0],
+                       [0, 1, 0, 0, 0],
+                       [0, 0, 0, 0, 0],
+                       [0, 0, 0, 0, 0]], np.uint8)
+    want_d = np.array([[1, 1, 1, 1, 0],
+                       [1, 1, 1, 1, 0],
+                       [1, 1, 1, 1, 1],
+                       [0, 1, 1, 1, 0]], np.uint8)
+    np.testing.assert_array_equal(omask.erode(img, plus, 1, 1), want_e)
+    np.testing.assert_array_equal(omask.dilate(img, plus, 1, 1), want_d)
+    empty = np.zeros((2, 2), np.uint8)
+    assert omask.erode(img, empty, 0, 0).all() and not omask.dilate(img, empty, 0, 0).any()
+
+
+def test_run_and_doubling_methods_match_definition():
+    for k in range(12):
+        r = np.random.default_rng(900 + k)
+        H, W = int(r.integers(1, 25)), int(r.integers(1, 80))
+        img = rnd_img(950 + k, H, W, float(r.choice([0.4, 0.7, 0.9])))
+        if k < 4:
+            m, cx, cy = omask.disc(int(r.integers(1, 5)))
+        else:
+            m, cx, cy = rnd_mask(960 + k, int(r.integers(1, 8)), int(r.integers(1, 40)))
+        want = omask.erode(img, m, cx, cy)
+        lines = otr.to_lines(*oracle.rle_encode(img))
+        got = omask.erode_lines_by_runs(lines, m, cx, cy, W)
+        np.testing.assert_array_equal(oracle.rle_decode(*otr.from_lines(got), W, H), want, err_msg=str(k))
+        np.testing.assert_array_equal(omask.erode_rows_by_doubling(img, m, cx, cy), want, err_msg=str(k))
