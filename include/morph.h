@@ -258,6 +258,39 @@ int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins
                                int32_t *out, void *ws, size_t ws_bytes, morph_stream_t stream);
 size_t morph_histogram_percentile_workspace_bytes(int32_t nbins);
 
+/* ---- arbitrary masks (section "Morphology with Arbitrary Masks") -------- */
+/*
+ * A mask is an h x w array of bytes in host memory (row-major, nonzero =
+ * pixel of the mask) with its origin (cx, cy) inside the frame:
+ *     erode (x,y) = AND of A(x + i - cx, y + j - cy) over the mask pixels (i, j)
+ *     dilate(x,y) = OR  of A(x - i + cx, y - j + cy) over the mask pixels
+ * with outside pixels 1 for erosion and 0 for dilation, as for rectangles
+ * (a full mask gives the rectangle operations); open and close compose them.
+ * An empty mask erodes to all 1s and dilates to all 0s.  The mask is read
+ * during the call only.  At most 256 horizontal runs, w and h below 32768
+ * (MORPH_E_UNSUPPORTED otherwise, also when a packed tile with the mask's
+ * halo does not fit in LDS).
+ */
+typedef struct {
+    const uint8_t *bits;
+    int32_t w, h, cx, cy;
+} morph_mask_t;
+/* Packed: the erosion is one launch that builds the horizontal erosions by
+ * 1, 2, 4, ... pixels of a tile in LDS and takes each mask run from the
+ * largest one not longer than it, at the run's two ends.  ws: for open and
+ * close one intermediate image, morph_mask_workspace_bytes(op, MORPH_PACKED,
+ * ...) bytes (256-byte aligned). */
+int morph_mask_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *src, const morph_mask_t *mask,
+                      void *ws, size_t ws_bytes, morph_stream_t stream);
+/* Run-length: one pass per mask run, intersecting the accumulated rows with
+ * the source rows dy below, eroded along the line by the run.  dst->capacity
+ * as for the rectangle operations; ws: morph_mask_workspace_bytes(op,
+ * MORPH_RLE, ...) bytes (256-byte aligned). */
+int morph_mask_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, const morph_mask_t *mask, void *ws,
+                   size_t ws_bytes, morph_stream_t stream);
+size_t morph_mask_workspace_bytes(int op, int repr, int32_t width, int32_t height, int32_t npages,
+                                  const morph_mask_t *mask);
+
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
  * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
@@ -348,7 +381,9 @@ enum {
     MORPH_K_COMPONENTS = 9,    /* connected-component labelling of runs (all its launches) */
     MORPH_K_COMPONENT_STATS = 10, /* per-component box, area and coordinate sums */
     MORPH_K_HISTOGRAM = 11,    /* run-length histograms */
-    MORPH_K_COUNT = 12
+    MORPH_K_MASK = 12,         /* packed erosion by an arbitrary mask */
+    MORPH_K_MASK_RLE = 13,     /* intersection with one eroded, shifted mask run on runs */
+    MORPH_K_COUNT = 14
 };
 typedef struct {
     int64_t launches;

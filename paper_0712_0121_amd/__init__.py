@@ -39,8 +39,10 @@ __all__ = [
     "morph_rect_rlet", "morph_rlet_workspace_bytes",
     "morph_rle_label", "morph_rle_label_workspace_bytes", "morph_rle_component_stats", "morph_component_t",
     "morph_rle_run_histograms", "morph_histogram_percentile", "morph_histogram_percentile_workspace_bytes",
+    "morph_mask_t", "morph_mask_packed", "morph_mask_rle", "morph_mask_workspace_bytes",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack", "transpose_packed", "transpose_rle", "rect_rlet",
     "label_components", "component_stats", "run_histograms", "histogram_percentile", "layout_boxes",
+    "Mask", "mask_packed", "mask_rle",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmorph.so")
@@ -75,11 +77,16 @@ class morph_component_t(ctypes.Structure):
                 ("area", ctypes.c_int64), ("sum_x", ctypes.c_int64), ("sum_y", ctypes.c_int64)]
 
 
+class morph_mask_t(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("w", ctypes.c_int32), ("h", ctypes.c_int32), ("cx", ctypes.c_int32),
+                ("cy", ctypes.c_int32)]
+
+
 class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 12
+MORPH_K_COUNT = 14
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -125,6 +132,10 @@ def _load():
         "morph_rle_run_histograms": (ctypes.c_int, [RL, P, P, P]),
         "morph_histogram_percentile": (ctypes.c_int, [P, I32, I32, I32, I32, P, P, SZ, P]),
         "morph_histogram_percentile_workspace_bytes": (SZ, [I32]),
+        "morph_mask_packed": (ctypes.c_int, [ctypes.c_int, BM, BM, ctypes.POINTER(morph_mask_t), P, SZ, P]),
+        "morph_mask_rle": (ctypes.c_int, [ctypes.c_int, RL, RL, ctypes.POINTER(morph_mask_t), P, SZ, P]),
+        "morph_mask_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, I32,
+                                            ctypes.POINTER(morph_mask_t)]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -420,6 +431,44 @@ def morph_histogram_percentile(hist, nrows, nbins, num, den, out, ws=None, strea
                                            p, n, _stream(stream)), "morph_histogram_percentile")
 
 
+class Mask:
+    """An arbitrary structuring element: an (h, w) array of 0/1 (host) and its
+    origin (cx, cy), column and row within the array."""
+
+    def __init__(self, bits, cx: int, cy: int):
+        import numpy as np
+        self.bits = np.ascontiguousarray(bits, dtype=np.uint8)
+        if self.bits.ndim != 2:
+            raise ValueError("mask must be 2-D (h, w)")
+        self.cx, self.cy = int(cx), int(cy)
+
+    def struct(self) -> morph_mask_t:
+        h, w = self.bits.shape
+        return morph_mask_t(self.bits.ctypes.data, w, h, self.cx, self.cy)
+
+
+def morph_mask_workspace_bytes(op, repr_, width, height, npages, mask: Mask) -> int:
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    m = mask.struct()
+    return int(_lib.morph_mask_workspace_bytes(op, int(repr_), int(width), int(height), int(npages), ctypes.byref(m)))
+
+
+def morph_mask_packed(op, dst: Bitmap, src: Bitmap, mask: Mask, ws=None, stream=None):
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    d, r, m = dst.struct(), src.struct(), mask.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_mask_packed(op, ctypes.byref(d), ctypes.byref(r), ctypes.byref(m), p, n, _stream(stream)),
+           "morph_mask_packed")
+
+
+def morph_mask_rle(op, dst: RLE, src: RLE, mask: Mask, ws=None, stream=None):
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    d, r, m = dst.struct(), src.struct(), mask.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_mask_rle(op, ctypes.byref(d), ctypes.byref(r), ctypes.byref(m), p, n, _stream(stream)),
+           "morph_mask_rle")
+
+
 class BatchPlan:
     """Many packed pages, each with its own operation and element, run as one
     persistent launch (morph_batch_plan_create / morph_batch_run)."""
@@ -647,3 +696,21 @@ def layout_boxes(src: RLE, num: int = 1, den: int = 3, connectivity: int = 8, st
     labels, comp_ptr = label_components(smeared, connectivity, stream)
     boxes, sums = component_stats(smeared, labels, comp_ptr, stream)
     return gx, gy, boxes, sums, comp_ptr
+
+
+def mask_packed(op: str, src: Bitmap, mask: Mask, dst: Bitmap | None = None, stream=None) -> Bitmap:
+    if dst is None:
+        dst = Bitmap.empty(src.width, src.height, src.npages, device=src.words.device)
+    ws = _alloc_ws(morph_mask_workspace_bytes(op, MORPH_PACKED, src.width, src.height, src.npages, mask),
+                   src.words.device)
+    morph_mask_packed(op, dst, src, mask, ws, stream)
+    return dst
+
+
+def mask_rle(op: str, src: RLE, mask: Mask, dst: RLE | None = None, stream=None) -> RLE:
+    if dst is None:
+        dst = RLE.empty(src.width, src.height, src.npages, device=src.row_ptr.device)
+    ws = _alloc_ws(morph_mask_workspace_bytes(op, MORPH_RLE, src.width, src.height, src.npages, mask),
+                   src.row_ptr.device)
+    morph_mask_rle(op, dst, src, mask, ws, stream)
+    return dst

@@ -825,6 +825,136 @@ int morph_histogram_percentile(const int32_t *hist, int32_t nrows, int32_t nbins
     return MORPH_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ masks
+namespace morph {
+
+static bool mask_ok(const morph_mask_t *m)
+{
+    return m && m->bits && m->w >= 1 && m->h >= 1 && m->w < 32768 && m->h < 32768 && m->cx >= 0 &&
+           m->cy >= 0 && m->cx < m->w && m->cy < m->h;
+}
+
+// The horizontal runs of the mask (or of its reflection), longest first.
+static bool mask_runs(const morph_mask_t &m, bool reflected, MaskRunsArg &out)
+{
+    struct Run { int dx, dy, len; };
+    std::vector<Run> v;
+    for (int j = 0; j < m.h; j++) {
+        int i = 0;
+        while (i < m.w) {
+            if (!m.bits[(size_t)j * m.w + i]) { i++; continue; }
+            int k = i;
+            while (k < m.w && m.bits[(size_t)j * m.w + k]) k++;
+            if (reflected)      // pixel (i, j) -> (w-1-i, h-1-j), origin -> (w-1-cx, h-1-cy)
+                v.push_back({(m.w - k) - (m.w - 1 - m.cx), (m.h - 1 - j) - (m.h - 1 - m.cy), k - i});
+            else
+                v.push_back({i - m.cx, j - m.cy, k - i});
+            i = k;
+        }
+    }
+    if ((int)v.size() > kMaskMaxRuns) return false;
+    std::stable_sort(v.begin(), v.end(), [](const Run &x, const Run &y) { return x.len > y.len; });
+    out.n = (int)v.size();
+    for (int q = 0; q < out.n; q++) {
+        out.dx[q] = (short)v[q].dx;
+        out.dy[q] = (short)v[q].dy;
+        out.len[q] = (short)v[q].len;
+    }
+    return true;
+}
+
+static bool mask_page(MaskPage &p, const morph_bitmap_t &dst, const morph_bitmap_t &src, int in_c, int out_c,
+                      const MaskRunsArg &m)
+{
+    p = MaskPage{};
+    p.src = src.words;
+    p.dst = dst.words;
+    p.W = src.width;
+    p.H = src.height;
+    p.nw = (src.width + 63) / 64;
+    p.sstride = src.stride_words;
+    p.dstride = dst.stride_words;
+    p.spw = (long long)src.stride_words * src.height;
+    p.dpw = (long long)dst.stride_words * dst.height;
+    p.in_c = in_c;
+    p.out_c = out_c;
+    p.padmask = (src.width % 64) ? ((1ull << (src.width % 64)) - 1) : ~0ull;
+    return plan_mask(p, m);
+}
+
+}  // namespace morph
+
+extern "C" {
+
+size_t morph_mask_workspace_bytes(int op, int repr, int32_t width, int32_t height, int32_t npages,
+                                  const morph_mask_t *mask)
+{
+    if (width < 1 || height < 1 || npages < 1 || !mask_ok(mask) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return 0;
+    const long long rows = (long long)height * npages;
+    if (repr == MORPH_PACKED)
+        return (op == MORPH_OPEN || op == MORPH_CLOSE) ? round256(image_bytes(width, (int)rows)) : 0;
+    return rle_mask_workspace(width, rows);
+}
+
+int morph_mask_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *src, const morph_mask_t *mask,
+                      void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    if (!bitmap_ok(dst) || !bitmap_ok(src) || !mask_ok(mask) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
+    MaskRunsArg m, mr;
+    if (!mask_runs(*mask, false, m) || !mask_runs(*mask, true, mr)) return MORPH_E_UNSUPPORTED;
+    const int W = src->width, H = src->height, P = src->npages;
+    const bool two = op == MORPH_OPEN || op == MORPH_CLOSE;
+    const size_t need = two ? round256(image_bytes(W, H * P)) : 0;
+    if (two && (!ws || (((uintptr_t)ws) & 255) || ws_bytes < need)) return MORPH_E_WORKSPACE;
+    const morph_bitmap_t tmp{(uint64_t *)ws, W, H, (W + 63) / 64, P};
+    if (two && (overlap(ws, need, dst->words, bitmap_extent(dst)) || overlap(ws, need, src->words, bitmap_extent(src))))
+        return MORPH_E_ALIAS;
+    // erosion by M; dilation = not erosion by the reflected mask of not A
+    struct Step { const morph_bitmap_t *d, *s; int in_c, out_c; const MaskRunsArg *m; };
+    Step steps[2];
+    int ns = 0;
+    switch (op) {
+    case MORPH_ERODE: steps[ns++] = {dst, src, 0, 0, &m}; break;
+    case MORPH_DILATE: steps[ns++] = {dst, src, 1, 1, &mr}; break;
+    case MORPH_OPEN: steps[ns++] = {&tmp, src, 0, 0, &m}; steps[ns++] = {dst, &tmp, 1, 1, &mr}; break;
+    default: steps[ns++] = {&tmp, src, 1, 1, &mr}; steps[ns++] = {dst, &tmp, 0, 0, &m}; break;
+    }
+    for (int k = 0; k < ns; k++) {
+        MaskPage p;
+        if (!mask_page(p, *steps[k].d, *steps[k].s, steps[k].in_c, steps[k].out_c, *steps[k].m))
+            return MORPH_E_UNSUPPORTED;
+        hipError_t e = launch_mask(p, *steps[k].m, P, (hipStream_t)stream);
+        if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    }
+    return MORPH_OK;
+}
+
+int morph_mask_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, const morph_mask_t *mask, void *ws,
+                   size_t ws_bytes, morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !rle_ok(src) || !mask_ok(mask) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    if (rle_alias(dst, src)) return MORPH_E_ALIAS;
+    const long long rows = (long long)src->height * src->npages;
+    if (rows * ((((long long)src->width + 1) / 2 + 15) & ~15LL) >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
+    MaskRunsArg m, mr;
+    if (!mask_runs(*mask, false, m) || !mask_runs(*mask, true, mr)) return MORPH_E_UNSUPPORTED;
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < rle_mask_workspace(src->width, rows)) return MORPH_E_WORKSPACE;
+    hipError_t e = rle_mask_op(op, *dst, *src, m, mr, ws, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
 {
     if (!rle_ok(r)) return MORPH_E_INVAL;
@@ -913,7 +1043,8 @@ const char *morph_kernel_name(int k)
                                                "rle_to_pack_kernel", "row_erode_kernel", "col_and_kernel",
                                                "pack_rows_kernel", "transpose_kernel",
                                                "decode_transpose_kernel", "components",
-                                               "component_stats_kernel", "run_hist_kernel"};
+                                               "component_stats_kernel", "run_hist_kernel", "mask_kernel",
+                                               "mask_and_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

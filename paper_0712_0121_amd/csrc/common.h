@@ -124,6 +124,30 @@ int device_cu_count();
 // height = src width).
 hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream);
 
+// ------------------------------------------------------------ arbitrary masks
+// The horizontal runs of a mask as offsets from its origin: run q covers
+// the pixels (dx[q] .. dx[q] + len[q] - 1, dy[q]) relative to the origin.
+constexpr int kMaskMaxRuns = 256;
+struct MaskRunsArg {
+    int n;
+    short dx[kMaskMaxRuns], dy[kMaskMaxRuns], len[kMaskMaxRuns];
+};
+
+// One erosion by a mask of npages stacked packed pages (complementing the
+// input and output when in_c / out_c), tiled as TR rows x SW words.
+struct MaskPage {
+    const uint64_t *src;
+    uint64_t *dst;
+    int W, H, nw, sstride, dstride;
+    long long spw, dpw;
+    int in_c, out_c;
+    uint64_t padmask;
+    int TR, SW, nbands, nstrips;
+    int HL, HR, dy0, NR, NW, levels;    // halo words, first row offset, LDS rows and words, doubling levels
+};
+bool plan_mask(MaskPage &p, const MaskRunsArg &m);
+hipError_t launch_mask(const MaskPage &p, const MaskRunsArg &m, int npages, hipStream_t stream);
+
 // ------------------------------------------------------------- run-length
 hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
                            hipStream_t stream);
@@ -132,6 +156,9 @@ size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t s
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 size_t scan_workspace(int64_t n);
+size_t rle_mask_workspace(int W, long long rows);
+hipError_t rle_mask_op(int op, const morph_rle_t &dst, const morph_rle_t &src, const MaskRunsArg &m,
+                       const MaskRunsArg &reflected, void *ws, hipStream_t s);
 // out[0..n] = exclusive scan of in[0..n-1], out[n] = total; tmp holds
 // scan_workspace(n) bytes.
 hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipStream_t s);

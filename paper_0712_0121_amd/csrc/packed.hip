@@ -603,6 +603,84 @@ __global__ __launch_bounds__(256) void transpose_kernel(
     }
 }
 
+
+// ----------------------------------------------------------- arbitrary masks
+// Erosion by an arbitrary mask, one workgroup per tile of TR rows x SW
+// words (section "Morphology with Arbitrary Masks", the doubling
+// accumulation): the tile's input rows with their halo are loaded into LDS
+// (outside pixels 1), the horizontal erosions by 1, 2, 4, ... pixels are
+// built in LDS level by level, and every output word is the AND over the
+// mask's runs of the erosion by the run's length, taken from the largest
+// level not longer than the run at the run's two ends, shifted by the run's
+// offsets.
+constexpr int kMaskLdsWords = 8192;     // 64 KiB of levels per workgroup
+
+// The 64 bits from bit position p of an LDS row of nwords words (1s past it).
+__device__ __forceinline__ uint64_t lds_bits(const uint64_t *row, int nwords, int p)
+{
+    const int w = p >> 6, s = p & 63;
+    if (w >= nwords) return kOnes;
+    const uint64_t lo = row[w];
+    if (s == 0) return lo;
+    const uint64_t hi = (w + 1 < nwords) ? row[w + 1] : kOnes;
+    return funnel_r(hi, lo, s);
+}
+
+__global__ __launch_bounds__(256) void mask_kernel(MaskPage P, MaskRunsArg M, long long ntiles)
+{
+    extern __shared__ uint64_t lv[];        // levels x NR x NW
+    const long long t = xcd_block();
+    if (t >= ntiles) return;                // whole workgroup
+    const long long per_page = (long long)P.nbands * P.nstrips;
+    const int page = (int)(t / per_page);
+    const int u = (int)(t - (long long)page * per_page);
+    const int band = u / P.nstrips, strip = u - band * P.nstrips;
+    const int y0 = band * P.TR, j0 = strip * P.SW;
+    const int TRv = min(P.TR, P.H - y0), SWv = min(P.SW, P.nw - j0);
+    const int NR = P.NR, NW = P.NW, plane = NR * NW;
+    const uint64_t inv = P.in_c ? kOnes : 0ull;
+    const uint64_t *sp = P.src + (long long)page * P.spw;
+    for (int i = threadIdx.x; i < plane; i += 256) {
+        const int r = i / NW, w = i - r * NW;
+        const int y = y0 + P.dy0 + r, j = j0 - P.HL + w;
+        uint64_t v = kOnes;
+        if (y >= 0 && y < P.H && j >= 0 && j < P.nw) {
+            v = sp[(long long)y * P.sstride + j] ^ inv;
+            if (j == P.nw - 1) v |= ~P.padmask;
+        }
+        lv[i] = v;
+    }
+    __syncthreads();
+    for (int l = 1; l < P.levels; l++) {    // E_{2^l}(x) = E_{2^(l-1)}(x) & E_{2^(l-1)}(x + 2^(l-1))
+        const uint64_t *prev = lv + (long long)(l - 1) * plane;
+        uint64_t *cur = lv + (long long)l * plane;
+        const int k = 1 << (l - 1);
+        for (int i = threadIdx.x; i < plane; i += 256) {
+            const int r = i / NW, w = i - r * NW;
+            cur[i] = prev[i] & lds_bits(prev + r * NW, NW, 64 * w + k);
+        }
+        __syncthreads();
+    }
+    const uint64_t outv = P.out_c ? kOnes : 0ull;
+    uint64_t *dp = P.dst + (long long)page * P.dpw;
+    for (int i = threadIdx.x; i < TRv * SWv; i += 256) {
+        const int r = i / SWv, c = i - r * SWv;
+        const int pbase = 64 * (c + P.HL);
+        uint64_t acc = kOnes;
+        for (int q = 0; q < M.n; q++) {
+            const int len = M.len[q];
+            const int l = 31 - __clz(len), m = 1 << l;
+            const uint64_t *row = lv + (long long)l * plane + (r + M.dy[q] - P.dy0) * NW;
+            const int p = pbase + M.dx[q];
+            acc &= lds_bits(row, NW, p) & lds_bits(row, NW, p + len - m);
+        }
+        const int j = j0 + c;
+        uint64_t o = acc ^ outv;
+        if (j == P.nw - 1) o &= P.padmask;
+        dp[(long long)(y0 + r) * P.dstride + j] = o;
+    }
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -765,6 +843,52 @@ hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src
                        src.stride_words, (long long)src.stride_words * H, pad, dst.words, dst.stride_words,
                        (long long)dst.stride_words * W, nw, nk, tiles_y, tiles_x, ntiles);
     trace_after(MORPH_K_TRANSPOSE, stream, 8.0 * src.npages * ((double)nw * H + (double)nk * W));
+    return hipGetLastError();
+}
+
+bool plan_mask(MaskPage &p, const MaskRunsArg &m)
+{
+    int dxmin = 0, reach = 0, dymin = 0, dymax = 0, maxlen = 1;
+    for (int q = 0; q < m.n; q++) {
+        if (m.len[q] < 1) return false;
+        dxmin = std::min(dxmin, (int)m.dx[q]);
+        reach = std::max(reach, m.dx[q] + m.len[q] - 1);
+        dymin = std::min(dymin, (int)m.dy[q]);
+        dymax = std::max(dymax, (int)m.dy[q]);
+        maxlen = std::max(maxlen, (int)m.len[q]);
+    }
+    int levels = 1;
+    while ((2 << (levels - 1)) <= maxlen) levels++;
+    p.HL = (-dxmin + 63) / 64;
+    p.HR = (reach + 63) / 64;
+    p.dy0 = dymin;
+    p.levels = levels;
+    int SW = std::min(p.nw, 8), TR = 64;
+    for (;;) {
+        p.NR = TR + dymax - dymin;
+        p.NW = SW + p.HL + p.HR;
+        if ((long long)levels * p.NR * p.NW <= kMaskLdsWords) break;
+        if (TR > 8) TR /= 2;
+        else if (SW > 1) SW /= 2;
+        else if (TR > 1) TR /= 2;
+        else return false;
+    }
+    p.TR = TR;
+    p.SW = SW;
+    p.nbands = (p.H + TR - 1) / TR;
+    p.nstrips = (p.nw + SW - 1) / SW;
+    return true;
+}
+
+hipError_t launch_mask(const MaskPage &p, const MaskRunsArg &m, int npages, hipStream_t stream)
+{
+    const long long ntiles = (long long)p.nbands * p.nstrips * npages;
+    if (ntiles <= 0) return hipSuccess;
+    if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = (size_t)p.levels * p.NR * p.NW * sizeof(uint64_t);
+    trace_before(MORPH_K_MASK, stream);
+    hipLaunchKernelGGL(mask_kernel, dim3((unsigned)ntiles), dim3(256), lds, stream, p, m, ntiles);
+    trace_after(MORPH_K_MASK, stream, 16.0 * p.nw * (double)p.H * npages);
     return hipGetLastError();
 }
 

@@ -912,6 +912,121 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
     }
 }
 
+// ----------------------------------------------------- arbitrary masks on runs
+// One run of a mask (section "Morphology with Arbitrary Masks", the
+// run-length form): output row y of a page is the intersection of the
+// accumulated row y with row y + dy of the source eroded along the line by
+// the run: pixel x survives when all of x + dx .. x + dx + len - 1 are 1,
+// pixels outside the line counting as 1.  A source row outside the page is
+// all 1s.  With comp the source is complemented first (its gaps are the
+// runs).  For the first run of a mask the accumulated row is the full row.
+struct MaskRunX {
+    int dx, dy, len, comp, W;
+};
+
+constexpr int kMaskBig = 1 << 30;           // stands for the infinite ends of border runs
+
+// Candidates of a source row (n raw runs R): its runs (or gaps), a run that
+// touches a border extended to infinity there, and the outside beyond each
+// border as a run of its own where no run touches it.
+__device__ __forceinline__ int mask_ncand(const MaskRunX &t, const int2 *R, int n)
+{
+    if (t.comp) return n + 1;
+    return n + ((n == 0 || R[0].x != 0) ? 1 : 0) + ((n == 0 || R[n - 1].y != t.W) ? 1 : 0);
+}
+
+__device__ __forceinline__ int2 mask_cand(const MaskRunX &t, const int2 *R, int n, int k)
+{
+    int s, e;
+    if (t.comp) {
+        s = k == 0 ? -kMaskBig : R[k - 1].y;
+        e = k == n ? kMaskBig : R[k].x;
+    } else {
+        const int i = k - ((n == 0 || R[0].x != 0) ? 1 : 0);
+        if (i < 0) {
+            s = -kMaskBig;
+            e = 0;
+        } else if (i == n) {
+            s = t.W;
+            e = kMaskBig;
+        } else {
+            s = R[i].x == 0 ? -kMaskBig : R[i].x;
+            e = R[i].y == t.W ? kMaskBig : R[i].y;
+        }
+    }
+    return make_int2(max(0, s - t.dx), min(t.W, e - t.dx - t.len + 1));
+}
+
+__global__ __launch_bounds__(256) void mask_and_kernel(RowsIn src, int P, int H, MaskRunX t, int first,
+                                                       const int *__restrict__ acc_cnt,
+                                                       const int *__restrict__ acc_runs, long long cap_row,
+                                                       int *__restrict__ out_cnt, int *__restrict__ out_runs,
+                                                       unsigned long long *trace)
+{
+    const long long r = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (r >= (long long)P * H) return;      // whole group
+    const int gl = glane();
+    const int page = (int)(r / H), y = (int)(r - (long long)page * H), ys = y + t.dy;
+    const bool outside = ys < 0 || ys >= H;
+    long long base = 0;
+    int n = 0;
+    if (!outside) row_span(src, (long long)page * H + ys, base, n);
+    const int2 *R = reinterpret_cast<const int2 *>(src.runs) + base;
+    const int nb = outside ? 1 : mask_ncand(t, R, n);
+    auto candB = [&](int k) { return outside ? make_int2(0, t.W) : mask_cand(t, R, n, k); };
+    int2 *o = reinterpret_cast<int2 *>(out_runs) + r * cap_row;
+    int carry = 0;
+    if (first) {                            // the live candidates, compacted
+        for (int k0 = 0; k0 < nb; k0 += kGroup) {
+            const int k = k0 + gl;
+            int2 c = make_int2(0, 0);
+            if (k < nb) c = candB(k);
+            const int l = live(c) ? 1 : 0;
+            const int inc = group_incl_scan(l);
+            const int idx = carry + inc - l;
+            if (l && idx < cap_row) o[idx] = c;
+            carry += group_last(inc);
+        }
+    } else {
+        const int2 *A = reinterpret_cast<const int2 *>(acc_runs) + r * cap_row;
+        const int na = min(max(acc_cnt[r], 0), (int)cap_row);
+        for (int k0 = 0; k0 < na; k0 += kGroup) {
+            const int k = k0 + gl;
+            int c = 0, span = 0, j0 = 0, sa = 0, ea = 0;
+            if (k < na) {
+                const int2 a = A[k];
+                sa = a.x;
+                ea = a.y;
+                int lo = 0, hi = nb;        // the first candidate that ends after sa
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (candB(mid).y > sa) hi = mid; else lo = mid + 1;
+                }
+                j0 = lo;
+                for (int j = j0; j < nb; j++) {
+                    const int2 b = candB(j);
+                    if (b.x >= ea) break;
+                    span++;
+                    c += live(b) ? 1 : 0;
+                }
+            }
+            const int inc = group_incl_scan(c);
+            int idx = carry + inc - c;
+            for (int j = j0; j < j0 + span; j++) {
+                const int2 b = candB(j);
+                if (!live(b)) continue;
+                if (idx < cap_row) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
+                idx++;
+            }
+            carry += group_last(inc);
+        }
+    }
+    if (gl == 0) {
+        out_cnt[r] = (int)min((long long)carry, cap_row);
+        if (trace) trace_add(trace, (unsigned long long)n, (unsigned long long)carry);
+    }
+}
+
 // Canonical-form check: sets *bad when a row breaks it.
 __global__ __launch_bounds__(256) void validate_kernel(const int *__restrict__ rp,
                                                        const int *__restrict__ runs, int R, int W,
@@ -1169,6 +1284,103 @@ hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, m
         if (e != hipSuccess) return e;
         b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, cx, cy, L, 1 - b, s, &e);
         return e != hipSuccess ? e : finish(L, b, 0, dst, W, s, false);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------ masks: host side
+// Workspace: three slot buffers (the accumulator alternates between two
+// that are not the chain's input), the final counts and scan scratch.
+struct MaskWs {
+    int *cnt[3];
+    int *runs[3];
+    int *fcount, *tmp;
+    long long cap_row;
+    size_t bytes;
+};
+
+static MaskWs mask_layout(void *base, int W, long long R)
+{
+    MaskWs L{};
+    L.cap_row = ((W + 1) / 2 + 15) & ~15LL;
+    char *p = (char *)base;
+    size_t off = 0;
+    auto take = [&](size_t b) { int *q = p ? (int *)(p + off) : nullptr; off += r256(b); return q; };
+    for (int i = 0; i < 3; i++) {
+        L.cnt[i] = take((size_t)R * 4);
+        L.runs[i] = take((size_t)R * L.cap_row * 8);
+    }
+    L.fcount = take((size_t)R * 4);
+    L.tmp = take(scan_workspace(R));
+    L.bytes = off;
+    return L;
+}
+
+size_t rle_mask_workspace(int W, long long R) { return mask_layout(nullptr, W, R).bytes; }
+
+// Erosion of P pages (or of their complements) by the mask runs m, into the
+// slot buffers other than `avoid`; returns the buffer with the result.
+static int mask_chain(const RowsIn &in, int comp, const MaskRunsArg &m, int P, int W, int H, const MaskWs &L,
+                      int avoid, hipStream_t s, hipError_t *err)
+{
+    const long long R = (long long)P * H;
+    unsigned long long *tr = trace_counters();
+    const int n = std::max(m.n, 1);
+    int cur = -1;
+    for (int q = 0; q < n; q++) {
+        int nxt = 0;
+        while (nxt == avoid || nxt == cur) nxt++;
+        // the empty mask: one pseudo-run whose source rows all lie outside
+        const MaskRunX t = m.n ? MaskRunX{m.dx[q], m.dy[q], m.len[q], comp, W} : MaskRunX{0, H, 1, comp, W};
+        trace_before(MORPH_K_MASK_RLE, s);
+        hipLaunchKernelGGL(mask_and_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, P, H, t,
+                           q == 0 ? 1 : 0, cur < 0 ? nullptr : L.cnt[cur], cur < 0 ? nullptr : L.runs[cur],
+                           (long long)L.cap_row, L.cnt[nxt], L.runs[nxt], trace_block(tr, MORPH_K_MASK_RLE));
+        trace_after(MORPH_K_MASK_RLE, s, 4.0 * R * (q == 0 ? 1 : 2));
+        cur = nxt;
+    }
+    *err = hipGetLastError();
+    return cur;
+}
+
+// erode: E_M(A); dilate: not E_M^(not A); open, close composed (the
+// reflected runs mr are those of the reflected mask).
+hipError_t rle_mask_op(int op, const morph_rle_t &dst, const morph_rle_t &src, const MaskRunsArg &m,
+                       const MaskRunsArg &mr, void *ws, hipStream_t s)
+{
+    const int P = src.npages, H = src.height, W = src.width;
+    const MaskWs L = mask_layout(ws, W, (long long)P * H);
+    const RowsIn in{src.row_ptr, nullptr, src.runs, (long long)src.capacity};
+    auto slot = [&](int i) { return RowsIn{nullptr, L.cnt[i], L.runs[i], L.cap_row}; };
+    auto fin = [&](int b, int comp) {
+        RleWs F{};
+        F.cnt[0] = L.cnt[b];
+        F.runs[0] = L.runs[b];
+        F.cnt[1] = F.runs[1] = nullptr;
+        F.fcount = L.fcount;
+        F.tmp = L.tmp;
+        F.cap_row = L.cap_row;
+        return finish(F, 0, comp, dst, W, s, false);
+    };
+    hipError_t e = hipSuccess;
+    int b;
+    switch (op) {
+    case MORPH_ERODE:
+        b = mask_chain(in, 0, m, P, W, H, L, -1, s, &e);
+        return e != hipSuccess ? e : fin(b, 0);
+    case MORPH_DILATE:
+        b = mask_chain(in, 1, mr, P, W, H, L, -1, s, &e);
+        return e != hipSuccess ? e : fin(b, 1);
+    case MORPH_OPEN:
+        b = mask_chain(in, 0, m, P, W, H, L, -1, s, &e);
+        if (e != hipSuccess) return e;
+        b = mask_chain(slot(b), 1, mr, P, W, H, L, b, s, &e);
+        return e != hipSuccess ? e : fin(b, 1);
+    case MORPH_CLOSE:
+        b = mask_chain(in, 1, mr, P, W, H, L, -1, s, &e);
+        if (e != hipSuccess) return e;
+        b = mask_chain(slot(b), 1, m, P, W, H, L, b, s, &e);
+        return e != hipSuccess ? e : fin(b, 0);
     }
     return hipErrorInvalidValue;
 }

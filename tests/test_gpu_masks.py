@@ -1,0 +1,125 @@
+"""GPU parity of erosion, dilation, opening and closing by arbitrary masks
+against the oracle's definition (one shifted AND / OR per mask pixel), on
+the packed path (words, pad bits masked) and the run-length path (row_ptr
+and runs exactly)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pagegen
+from gpu_util import blobs_img, garbage_pad, require_gpu, rnd_img
+from oracle import masks as omask
+
+pytestmark = pytest.mark.gpu
+
+M = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    require_gpu()
+    global M
+    import paper_0712_0121_amd as m
+    M = m
+    return m
+
+
+def run_both(op, img, bits, cx, cy, npages=1):
+    rows, W = img.shape
+    words = garbage_pad(oracle.pack(img, (W + 63) // 64 + 1), W, 5)
+    src = M.Bitmap.from_words(words, W, npages=npages)
+    mk = M.Mask(bits, cx, cy)
+    pk = M.mask_packed(op, src, mk)
+    rl = M.mask_rle(op, M.pack_to_rle(src), mk)
+    torch.cuda.synchronize()
+    return pk.to_numpy(), rl.to_host()
+
+
+def check(op, img, bits, cx, cy, what="", npages=1):
+    H = img.shape[0] // npages
+    want = np.concatenate([omask.apply(op, img[p * H:(p + 1) * H], bits, cx, cy) for p in range(npages)])
+    pk, (rp, runs) = run_both(op, img, bits, cx, cy, npages)
+    np.testing.assert_array_equal(pk, oracle.pack(want), err_msg="packed " + what)
+    wrp, wruns = oracle.rle_encode(want)
+    np.testing.assert_array_equal(rp, wrp, err_msg="runs row_ptr " + what)
+    np.testing.assert_array_equal(runs, wruns, err_msg="runs " + what)
+
+
+def masks():
+    out = []
+    for r in (1, 2, 5):
+        d, cx, cy = omask.disc(r)
+        out.append(("disc%d" % r, d, cx, cy))
+    plus = np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]], np.uint8)
+    out.append(("plus", plus, 1, 1))
+    out.append(("ring", (omask.disc(4)[0] - np.pad(omask.disc(2)[0], 2)).astype(np.uint8), 4, 4))
+    out.append(("shift", np.array([[1]], np.uint8), 0, 0))
+    out.append(("pixel_offcentre", np.array([[0, 0, 0], [0, 0, 1]], np.uint8), 0, 0))
+    out.append(("rect_corner_origin", np.ones((4, 6), np.uint8), 5, 0))
+    r = np.random.default_rng(8)
+    out.append(("random", (r.random((5, 9)) < 0.5).astype(np.uint8), 2, 3))
+    out.append(("empty", np.zeros((2, 3), np.uint8), 1, 1))
+    out.append(("long_line", np.ones((1, 150), np.uint8), 0, 0))
+    out.append(("tall_bar", np.ones((45, 2), np.uint8), 1, 44))
+    return out
+
+
+MASKS = masks()
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+@pytest.mark.parametrize("mk", MASKS, ids=lambda m: m[0])
+def test_masks_small_page(op, mk):
+    name, bits, cx, cy = mk
+    img = blobs_img(len(name) * 7, 70, 200, 0.45)
+    check(op, img, bits, cx, cy, "%s %s" % (op, name))
+
+
+@pytest.mark.parametrize("W", [1, 63, 64, 65, 130, 700])
+def test_masks_widths_and_borders(W):
+    img = rnd_img(W, 37, W, 0.7)
+    d, cx, cy = omask.disc(3)
+    for op in pagegen.OPS:
+        check(op, img, d, cx, cy, "W=%d %s" % (W, op))
+    full = rnd_img(1, 20, W, 1.0)
+    for op in pagegen.OPS:
+        check(op, full, d, cx, cy, "full W=%d %s" % (W, op))
+
+
+def test_masks_stacked_pages():
+    P, H, W = 3, 50, 150
+    img = np.concatenate([blobs_img(300 + k, H, W, 0.5) for k in range(P)])
+    d, cx, cy = omask.disc(4)
+    for op in pagegen.OPS:
+        check(op, img, d, cx, cy, "stacked " + op, npages=P)
+
+
+def test_mask_full_equals_rectangle_path():
+    img = blobs_img(11, 90, 300, 0.4)
+    W = img.shape[1]
+    src = M.Bitmap.from_words(oracle.pack(img), W)
+    for op in pagegen.OPS:
+        se = (7, 5, 2, 4)
+        a = M.mask_packed(op, src, M.Mask(np.ones((5, 7), np.uint8), 2, 4)).to_numpy()
+        b = M.rect_packed(op, src, se).to_numpy()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+def test_masks_letter_page(op):
+    img = pagegen.letter_page(2000).img
+    d, cx, cy = omask.disc(6)
+    check(op, img, d, cx, cy, "letter disc6 " + op)
+
+
+def test_too_many_runs_is_unsupported():
+    img = rnd_img(1, 10, 10, 0.5)
+    bits = np.zeros((300, 3), np.uint8)
+    bits[:, 0] = 1
+    bits[:, 2] = 1                                   # 600 runs
+    src = M.Bitmap.from_words(oracle.pack(img), 10)
+    with pytest.raises(M.MorphError) as e:
+        M.mask_packed("erode", src, M.Mask(bits, 0, 0))
+    assert e.value.code == -8
