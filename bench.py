@@ -15,8 +15,8 @@ events inside the timed region, and the CPU oracle timed on a sample of the
 same work.  Pages are synthetic (seeded), standing in for scanned 300 dpi
 letter pages.  Extras beside the step (outside `value`): the mixed batch in
 one persistent launch, the representation choice, the serving loop,
-transposition and the transpose-based operations, and connected components
-with the layout composition.
+transposition and the transpose-based operations, connected components
+with the layout composition, and operations by disc-shaped masks.
 """
 from __future__ import annotations
 
@@ -45,9 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
-    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose", "components"], default="all",
-                    help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose' and "
-                         "'components' print only those measurements")
+    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose", "components", "masks"], default="all",
+                    help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose', "
+                         "'components' and 'masks' print only those measurements")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -355,6 +355,48 @@ def bench_components(M, dev, src):
     return out
 
 
+MASK_RADII = (3, 10)
+
+
+def bench_masks(M, dev, src):
+    """Erosion, dilation, opening and closing of the letter batch by discs of
+    radius 3 and 10 (7 x 7 and 21 x 21 masks), on both paths: Gpixel/s, and
+    for the packed kernel the algorithmic bytes (one read and one write of
+    the batch per operation) against the HBM peak."""
+    import torch
+    W, H, B = src.width, src.height, src.npages
+    nw = (W + 63) // 64
+    r_in = M.RLE.empty(W, H, B, device=dev)
+    ws_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * B), dtype=torch.uint8, device=dev)
+    M.morph_pack_to_rle(r_in, src, ws_p2r)
+    del ws_p2r
+    dst = M.Bitmap.empty(W, H, B, device=dev)
+    r_out = M.RLE.empty(W, H, B, device=dev)
+    px = W * H * B
+    alg = 16.0 * nw * H * B
+    out = {"pages": B}
+    for rad in MASK_RADII:
+        j, i = np.mgrid[0:2 * rad + 1, 0:2 * rad + 1]
+        mk = M.Mask(((i - rad) ** 2 + (j - rad) ** 2 <= rad * rad).astype(np.uint8), rad, rad)
+        ws_pk = torch.empty(max(M.morph_mask_workspace_bytes("open", 0, W, H, B, mk), 256), dtype=torch.uint8,
+                            device=dev)
+        ws_rl = torch.empty(M.morph_mask_workspace_bytes("open", 1, W, H, B, mk), dtype=torch.uint8, device=dev)
+        res = {}
+        for op in OPS:
+            tp = time_ms(lambda: M.morph_mask_packed(op, dst, src, mk, ws_pk), 3)
+            tr = time_ms(lambda: M.morph_mask_rle(op, r_out, r_in, mk, ws_rl), 2)
+            launches = 2 if op in ("open", "close") else 1
+            res[op] = {"packed_ms": round(tp, 4), "rle_ms": round(tr, 4),
+                       "packed_gpixel_s": px / (tp / 1e3) / 1e9, "rle_gpixel_s": px / (tr / 1e3) / 1e9,
+                       "packed_hbm_frac": launches * alg / (tp / 1e3) / 1e9 / HBM_PEAK_GBS}
+        out["disc%d" % rad] = res
+        del ws_pk, ws_rl
+        torch.cuda.empty_cache()
+    del r_in, r_out, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_repr(M, dev, tuner):
     """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
     (conversions included), as the autotuner records it."""
@@ -385,9 +427,10 @@ def main():
     words_pool = [torch.from_numpy(p.words().view(np.int64)) for p in pool]
     host = torch.cat([words_pool[i % len(pool)] for i in range(B)], dim=0)
     src = M.Bitmap(host.to(dev), W, H, B)
-    if args.only in ("transpose", "components"):
+    if args.only in ("transpose", "components", "masks"):
         del host
-        res = bench_transpose(M, dev, src, None) if args.only == "transpose" else bench_components(M, dev, src)
+        res = {"transpose": lambda: bench_transpose(M, dev, src, None), "components": lambda: bench_components(M, dev, src),
+               "masks": lambda: bench_masks(M, dev, src)}[args.only]()
         # the elementwise copy whose HBM counters calibrate the profiles
         cal = torch.empty_like(src.words)
         torch.bitwise_or(src.words, 0, out=cal)
@@ -578,6 +621,7 @@ def main():
         out["serving"] = bench_serving(M, dev, args.serve_seconds)
         out["transpose"] = bench_transpose(M, dev, src, breakdown.get("rle", {}).get("ms_per_op"))
         out["components"] = bench_components(M, dev, src)
+        out["masks"] = bench_masks(M, dev, src)
         try:
             tuner.save()
         except OSError:

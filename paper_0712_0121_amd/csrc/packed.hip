@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(
 // mask's runs of the erosion by the run's length, taken from the largest
 // level not longer than the run at the run's two ends, shifted by the run's
 // offsets.
-constexpr int kMaskLdsWords = 8192;     // 64 KiB of levels per workgroup
+constexpr int kMaskLdsWords = 4096;     // 32 KiB of levels per workgroup (4 per CU)
 
 // The 64 bits from bit position p of an LDS row of nwords words (1s past it).
 __device__ __forceinline__ uint64_t lds_bits(const uint64_t *row, int nwords, int p)

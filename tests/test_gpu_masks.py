@@ -123,3 +123,33 @@ def test_too_many_runs_is_unsupported():
     with pytest.raises(M.MorphError) as e:
         M.mask_packed("erode", src, M.Mask(bits, 0, 0))
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+def test_masks_letter_batch_as_timed(op):
+    """The benchmark's batch: 256 stacked letter pages (16 distinct,
+    replicated) with the discs of radius 3 and 10, on both paths: two
+    distinct pages whole against the oracle's definition, every page's runs
+    against its packed result, every replica against its original."""
+    B, D = 256, 16
+    pool = [pagegen.letter_page(2000 + i) for i in range(D)]
+    W, H = 2550, 3300
+    host = np.concatenate([pool[i % D].words() for i in range(B)])
+    src = M.Bitmap.from_words(host, W, npages=B)
+    del host
+    r_in = M.pack_to_rle(src)
+    for rad in (3, 10):
+        d, cx, cy = omask.disc(rad)
+        mk = M.Mask(d, cx, cy)
+        pk = M.mask_packed(op, src, mk)
+        rl = M.mask_rle(op, r_in, mk)
+        back = M.rle_to_pack(rl)
+        torch.cuda.synchronize()
+        assert torch.equal(back.words, pk.words), "runs vs packed, disc %d" % rad
+        words = pk.to_numpy().reshape(B, H, -1)
+        for i in (0, 5):
+            want = oracle.pack(omask.apply(op, pool[i].img, d, cx, cy))
+            np.testing.assert_array_equal(words[i], want, err_msg="%s disc%d page %d" % (op, rad, i))
+        for i in range(D, B):
+            np.testing.assert_array_equal(words[i], words[i % D], err_msg="replica %d" % i)
+        del pk, rl, back, words
