@@ -249,3 +249,36 @@ def test_component_argument_errors():
     wal = (wsb.ptr + 255) & ~255
     assert P(b.ptr, 1, 10, 1, 2, c.ptr, wal, pw - 1) == -4
     assert ctypes.sizeof(M.morph_component_t) == 40
+
+
+def test_mask_argument_errors():
+    a, b = HostBuf(1 << 16), HostBuf(1 << 16)
+    bits = np.ones((3, 3), np.uint8)
+    mk = M.morph_mask_t(bits.ctypes.data, 3, 3, 1, 1)
+    bad_origin = M.morph_mask_t(bits.ctypes.data, 3, 3, 3, 1)
+    null_bits = M.morph_mask_t(None, 3, 3, 1, 1)
+    many = np.zeros((300, 3), np.uint8)
+    many[:, 0] = 1
+    many[:, 2] = 1
+    too_many = M.morph_mask_t(many.ctypes.data, 3, 300, 0, 0)
+    MP = lambda op, d, s, m, ws=None, n=0: M._lib.morph_mask_packed(op, ctypes.byref(d), ctypes.byref(s),
+                                                                     ctypes.byref(m), ws, n, None)
+    assert MP(0, bitmap(a, 100, 10), bitmap(b, 100, 10), bad_origin) == -1
+    assert MP(0, bitmap(a, 100, 10), bitmap(b, 100, 10), null_bits) == -1
+    assert MP(7, bitmap(a, 100, 10), bitmap(b, 100, 10), mk) == -1
+    assert MP(0, bitmap(a, 100, 11), bitmap(b, 100, 10), mk) == -2
+    assert MP(0, bitmap(a, 100, 10), bitmap(a, 100, 10), mk) == -3
+    assert MP(2, bitmap(a, 100, 10), bitmap(b, 100, 10), mk) == -4             # opening needs its image
+    assert MP(0, bitmap(a, 100, 10), bitmap(b, 100, 10), too_many) == -8
+    assert M._lib.morph_mask_workspace_bytes(2, 0, 100, 10, 1, ctypes.byref(mk)) >= 2 * 10 * 8
+    assert M._lib.morph_mask_workspace_bytes(0, 0, 100, 10, 1, ctypes.byref(mk)) == 0
+    W, H = 100, 10
+    cap = M.morph_rle_max_runs(W, H)
+    MR = lambda op, d, s, m, ws=None, n=0: M._lib.morph_mask_rle(op, ctypes.byref(d), ctypes.byref(s),
+                                                                  ctypes.byref(m), ws, n, None)
+    assert MR(0, rle(a, W, H, cap), rle(b, W, H, cap), bad_origin) == -1
+    assert MR(0, rle(a, W, H, cap), rle(b, W + 1, H, cap), mk) == -2
+    assert MR(0, rle(a, W, H, cap), rle(a, W, H, cap), mk) == -3
+    assert MR(0, rle(a, W, H, cap - 1), rle(b, W, H, cap), mk) == -6
+    assert MR(0, rle(a, W, H, cap), rle(b, W, H, cap), mk) == -4
+    assert MR(0, rle(a, W, H, cap), rle(b, W, H, cap), too_many) == -8
