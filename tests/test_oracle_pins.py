@@ -700,3 +700,55 @@ def test_run_and_doubling_methods_match_definition():
         got = omask.erode_lines_by_runs(lines, m, cx, cy, W)
         np.testing.assert_array_equal(oracle.rle_decode(*otr.from_lines(got), W, H), want, err_msg=str(k))
         np.testing.assert_array_equal(omask.erode_rows_by_doubling(img, m, cx, cy), want, err_msg=str(k))
+
+
+# ---------------------------------------------------------- skews, rotation
+from oracle import shear as osh  # noqa: E402
+
+
+def _crop(a):
+    ys, xs = np.nonzero(a)
+    return a[ys.min():ys.max() + 1, xs.min():xs.max() + 1]
+
+
+def test_shift_rows_against_slicing_and_inverse():
+    img = rnd_img(21, 17, 40, 0.5)
+    for s, fill in [(0, 0), (5, 0), (-7, 1), (39, 1), (-40, 0), (60, 0)]:
+        got = osh.shift_rows(img, [s] * 17, 40, fill)
+        want = np.full_like(img, fill)
+        if s >= 0:
+            want[:, s:] = img[:, :40 - s] if s < 40 else want[:, s:]
+        else:
+            want[:, :40 + s] = img[:, -s:]
+        np.testing.assert_array_equal(got, want, err_msg=str(s))
+    sk, s = osh.skew_rows(img, 3, 7, 5)
+    assert sk.shape == (17, 40 + int(s.max()))
+    np.testing.assert_array_equal(osh.shift_rows(sk, -s, 40, 0), img)
+    assert list(osh.skew_shifts(4, -3, 2, 1)) == [1, 0, -2, -3]        # floor division
+
+
+def test_rotation_by_ninety_degrees_and_zero():
+    img = np.zeros((21, 30), np.uint8)
+    img[3:8, 4:20] = 1
+    img[10:18, 22:25] = 1
+    img[15, 2] = 1
+    rot = osh.rotate(img, 1 << 16, 1 << 16, 1 << 16)   # tan 45 = 1, sin 90 = 1: exact skews
+    np.testing.assert_array_equal(_crop(rot), _crop(np.rot90(img, -1)))
+    np.testing.assert_array_equal(osh.rotate(img, 0, 0, 1 << 16), img)
+    assert rot.sum() == img.sum()
+
+
+def test_line_op_horizontal_is_the_rectangle_and_diagonal_by_hand():
+    img = rnd_img(4, 25, 31, 0.7)
+    for op in ("erode", "dilate"):
+        np.testing.assert_array_equal(osh.line_op(op, img, 5, 0, 1), oracle.apply(op, img, (5, 1, 2, 0)))
+    diag = np.zeros((9, 9), np.uint8)
+    for k in range(1, 8):
+        diag[k, k] = 1
+    # a 3-pixel line at slope 1 (down-right): the diagonal keeps its inner pixels
+    er = osh.line_op("erode", diag, 3, 1, 1)
+    assert [(y, x) for y, x in zip(*np.nonzero(er))] == [(k, k) for k in range(2, 7)]
+    single = np.zeros((9, 9), np.uint8)
+    single[4, 4] = 1
+    di = osh.line_op("dilate", single, 3, 1, 1)
+    assert [(y, x) for y, x in zip(*np.nonzero(di))] == [(3, 3), (4, 4), (5, 5)]
