@@ -291,6 +291,26 @@ int morph_mask_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, const
 size_t morph_mask_workspace_bytes(int op, int repr, int32_t width, int32_t height, int32_t npages,
                                   const morph_mask_t *mask);
 
+/* ---- line shifts (section "Scaling, Skewing, and Rotation") ------------- */
+/*
+ * Every line moves right by its own shift: dst(x, y) = src(x - shifts[r], y)
+ * where that lies inside the source line, fill (0 or 1) elsewhere; r counts
+ * the rows of all stacked pages.  shifts: device int32, height * npages
+ * entries (values are clamped to +-2^30).  dst and src must agree in height
+ * and npages; their widths may differ (a skew that keeps every pixel needs a
+ * wider destination).  Skews with any slope, skews across the lines (by
+ * transposing), rotation by three skews and line operations at an angle
+ * are sequences of these calls.
+ */
+int morph_shift_rows_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, const int32_t *shifts,
+                            int32_t fill, morph_stream_t stream);
+/* Run-length form; dst->capacity >= morph_rle_max_runs(dst width, rows);
+ * ws: morph_shift_rows_rle_workspace_bytes(height * npages) bytes, 256-byte
+ * aligned. */
+int morph_shift_rows_rle(const morph_rle_t *dst, const morph_rle_t *src, const int32_t *shifts, int32_t fill,
+                         void *ws, size_t ws_bytes, morph_stream_t stream);
+size_t morph_shift_rows_rle_workspace_bytes(int32_t rows);
+
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
  * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
@@ -383,7 +403,9 @@ enum {
     MORPH_K_HISTOGRAM = 11,    /* run-length histograms */
     MORPH_K_MASK = 12,         /* packed erosion by an arbitrary mask */
     MORPH_K_MASK_RLE = 13,     /* intersection with one eroded, shifted mask run on runs */
-    MORPH_K_COUNT = 14
+    MORPH_K_SHIFT = 14,        /* packed line shifts */
+    MORPH_K_SHIFT_RLE = 15,    /* line shifts on runs (count and emit launches) */
+    MORPH_K_COUNT = 16
 };
 typedef struct {
     int64_t launches;

@@ -40,9 +40,11 @@ __all__ = [
     "morph_rle_label", "morph_rle_label_workspace_bytes", "morph_rle_component_stats", "morph_component_t",
     "morph_rle_run_histograms", "morph_histogram_percentile", "morph_histogram_percentile_workspace_bytes",
     "morph_mask_t", "morph_mask_packed", "morph_mask_rle", "morph_mask_workspace_bytes",
+    "morph_shift_rows_packed", "morph_shift_rows_rle", "morph_shift_rows_rle_workspace_bytes",
     "rect_packed", "rect_rle", "pack_to_rle", "rle_to_pack", "transpose_packed", "transpose_rle", "rect_rlet",
     "label_components", "component_stats", "run_histograms", "histogram_percentile", "layout_boxes",
     "Mask", "mask_packed", "mask_rle",
+    "shift_rows", "skew_rows", "skew_cols", "rotate", "rotation_rationals", "line_op",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmorph.so")
@@ -86,7 +88,7 @@ class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 14
+MORPH_K_COUNT = 16
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -136,6 +138,9 @@ def _load():
         "morph_mask_rle": (ctypes.c_int, [ctypes.c_int, RL, RL, ctypes.POINTER(morph_mask_t), P, SZ, P]),
         "morph_mask_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, I32,
                                             ctypes.POINTER(morph_mask_t)]),
+        "morph_shift_rows_packed": (ctypes.c_int, [BM, BM, P, I32, P]),
+        "morph_shift_rows_rle": (ctypes.c_int, [RL, RL, P, I32, P, SZ, P]),
+        "morph_shift_rows_rle_workspace_bytes": (SZ, [I32]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -469,6 +474,23 @@ def morph_mask_rle(op, dst: RLE, src: RLE, mask: Mask, ws=None, stream=None):
            "morph_mask_rle")
 
 
+def morph_shift_rows_packed(dst: Bitmap, src: Bitmap, shifts, fill: int, stream=None):
+    d, r = dst.struct(), src.struct()
+    _check(_lib.morph_shift_rows_packed(ctypes.byref(d), ctypes.byref(r), _ptr(shifts), int(fill), _stream(stream)),
+           "morph_shift_rows_packed")
+
+
+def morph_shift_rows_rle_workspace_bytes(rows) -> int:
+    return int(_lib.morph_shift_rows_rle_workspace_bytes(int(rows)))
+
+
+def morph_shift_rows_rle(dst: RLE, src: RLE, shifts, fill: int, ws=None, stream=None):
+    d, r = dst.struct(), src.struct()
+    p, n = _ws(ws)
+    _check(_lib.morph_shift_rows_rle(ctypes.byref(d), ctypes.byref(r), _ptr(shifts), int(fill), p, n,
+                                     _stream(stream)), "morph_shift_rows_rle")
+
+
 class BatchPlan:
     """Many packed pages, each with its own operation and element, run as one
     persistent launch (morph_batch_plan_create / morph_batch_run)."""
@@ -714,3 +736,92 @@ def mask_rle(op: str, src: RLE, mask: Mask, dst: RLE | None = None, stream=None)
                    src.row_ptr.device)
     morph_mask_rle(op, dst, src, mask, ws, stream)
     return dst
+
+
+# ------------------------------------------------- skews, rotation, lines
+# The image work of these compositions runs in the library (line shifts,
+# transposes, rectangle operations); the host only computes the integer
+# shift of each line, as it computes an element or a launch.
+def shift_rows(src, shifts, width: int, fill: int = 0, stream=None):
+    """Every line moves right by its shift (device int32, one per line of all
+    pages): dst(x, y) = src(x - shift, y) inside the source, fill elsewhere."""
+    if isinstance(src, Bitmap):
+        dst = Bitmap.empty(width, src.height, src.npages, device=src.words.device)
+        morph_shift_rows_packed(dst, src, shifts, fill, stream)
+        return dst
+    dst = RLE.empty(width, src.height, src.npages, device=src.row_ptr.device)
+    ws = _alloc_ws(morph_shift_rows_rle_workspace_bytes(src.height * src.npages), src.row_ptr.device)
+    morph_shift_rows_rle(dst, src, shifts, fill, ws, stream)
+    return dst
+
+
+def _dev(img):
+    return img.words.device if isinstance(img, Bitmap) else img.row_ptr.device
+
+
+def _transpose(img, stream=None):
+    return transpose_packed(img, stream) if isinstance(img, Bitmap) else transpose_rle(img, stream)
+
+
+def skew_rows(src, num: int, den: int, origin: int, fill: int = 0, stream=None):
+    """Lossless skew along the lines: line y moves by floor(num (y - origin) /
+    den), less the smallest such shift; the frame widens by their spread.
+    Returns (image, shifts as a numpy array)."""
+    import numpy as np
+    if den <= 0:
+        raise ValueError("den must be positive")
+    v = (num * (np.arange(src.height, dtype=np.int64) - origin)) // den
+    v = v - v.min()
+    shifts = torch.from_numpy(np.tile(v, src.npages).astype(np.int32)).to(_dev(src))
+    return shift_rows(src, shifts, src.width + int(v.max()), fill, stream), v
+
+
+def skew_cols(src, num: int, den: int, origin: int, fill: int = 0, stream=None):
+    """Lossless skew across the lines (column x moves down by floor(num (x -
+    origin) / den) less the smallest): transpose, skew the lines, transpose."""
+    t, v = skew_rows(_transpose(src, stream), num, den, origin, fill, stream)
+    return _transpose(t, stream), v
+
+
+def rotation_rationals(angle: float, den: int = 1 << 16):
+    """(tan_num, sin_num, den): tan(angle / 2) and sin(angle) as rationals."""
+    import math
+    return int(round(math.tan(angle / 2) * den)), int(round(math.sin(angle) * den)), den
+
+
+def rotate(src, tan_num: int, sin_num: int, den: int, stream=None):
+    """Rotation by three lossless skews about the frame centre (along the
+    lines by -tan(a/2), across them by sin(a), along them by -tan(a/2)); the
+    frame grows to hold every pixel."""
+    a, _ = skew_rows(src, -tan_num, den, src.height // 2, 0, stream)
+    a, _ = skew_cols(a, sin_num, den, a.width // 2, 0, stream)
+    a, _ = skew_rows(a, -tan_num, den, a.height // 2, 0, stream)
+    return a
+
+
+def line_op(op: str, src, length: int, num: int, den: int, stream=None):
+    """Erosion or dilation by a centred line of `length` pixels along the
+    slope num/den (|num| <= den): the columns skewed so that the line becomes
+    horizontal (pixels brought in from outside take the border value: 1 for
+    erosion, 0 for dilation), the horizontal operation, and the inverse skew
+    into the original frame."""
+    import numpy as np
+    if op not in ("erode", "dilate"):
+        raise ValueError("line_op: erode or dilate")
+    if abs(num) > den:
+        raise ValueError("line_op: |slope| must be at most 1 (transpose for steeper lines)")
+    dev = _dev(src)
+    fill = 1 if op == "erode" else 0
+    W, H, P = src.width, src.height, src.npages
+    v = np.array([-((num * x) // den) for x in range(W)], dtype=np.int64)
+    off = -int(v.min())
+    Ht = H + int(v.max()) + off
+    fwd = torch.from_numpy(np.tile(v + off, P).astype(np.int32)).to(dev)
+    back = torch.from_numpy(np.tile(-(v + off), P).astype(np.int32)).to(dev)
+    t = _transpose(src, stream)                            # W lines of length H per page
+    sk = shift_rows(t, fwd, Ht, fill, stream)
+    flat = _transpose(sk, stream)                          # Ht x W: the line is horizontal
+    se_ = (length, 1, length // 2, 0)
+    res = rect_packed(op, flat, se_, stream=stream) if isinstance(flat, Bitmap) else rect_rle(op, flat, se_, stream=stream)
+    t2 = _transpose(res, stream)
+    return _transpose(shift_rows(t2, back, H, 0, stream), stream)

@@ -955,6 +955,40 @@ int morph_mask_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, const
     return MORPH_OK;
 }
 
+int morph_shift_rows_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, const int32_t *shifts,
+                            int32_t fill, morph_stream_t stream)
+{
+    if (!bitmap_ok(dst) || !bitmap_ok(src) || !shifts || (((uintptr_t)shifts) & 3) || (fill != 0 && fill != 1))
+        return MORPH_E_INVAL;
+    if (dst->height != src->height || dst->npages != src->npages) return MORPH_E_SHAPE;
+    if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src)) ||
+        overlap(dst->words, bitmap_extent(dst), shifts, (size_t)src->height * src->npages * 4))
+        return MORPH_E_ALIAS;
+    hipError_t e = shift_rows_packed(*dst, *src, shifts, fill, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
+size_t morph_shift_rows_rle_workspace_bytes(int32_t rows)
+{
+    return rows < 1 ? 0 : shift_rows_rle_workspace(rows);
+}
+
+int morph_shift_rows_rle(const morph_rle_t *dst, const morph_rle_t *src, const int32_t *shifts, int32_t fill,
+                         void *ws, size_t ws_bytes, morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !rle_ok(src) || !shifts || (((uintptr_t)shifts) & 3) || (fill != 0 && fill != 1))
+        return MORPH_E_INVAL;
+    if (dst->height != src->height || dst->npages != src->npages) return MORPH_E_SHAPE;
+    if (rle_alias(dst, src)) return MORPH_E_ALIAS;
+    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
+    const long long R = (long long)src->height * src->npages;
+    if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < shift_rows_rle_workspace(R)) return MORPH_E_WORKSPACE;
+    hipError_t e = shift_rows_rle(*dst, *src, shifts, fill, ws, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 int morph_rle_validate(const morph_rle_t *r, morph_stream_t stream)
 {
     if (!rle_ok(r)) return MORPH_E_INVAL;
@@ -1044,7 +1078,7 @@ const char *morph_kernel_name(int k)
                                                "pack_rows_kernel", "transpose_kernel",
                                                "decode_transpose_kernel", "components",
                                                "component_stats_kernel", "run_hist_kernel", "mask_kernel",
-                                               "mask_and_kernel"};
+                                               "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

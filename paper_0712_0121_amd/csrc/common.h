@@ -156,6 +156,11 @@ size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t s
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 size_t scan_workspace(int64_t n);
+hipError_t shift_rows_packed(const morph_bitmap_t &dst, const morph_bitmap_t &src, const int *shifts, int fill,
+                             hipStream_t s);
+size_t shift_rows_rle_workspace(long long rows);
+hipError_t shift_rows_rle(const morph_rle_t &dst, const morph_rle_t &src, const int *shifts, int fill, void *ws,
+                          hipStream_t s);
 size_t rle_mask_workspace(int W, long long rows);
 hipError_t rle_mask_op(int op, const morph_rle_t &dst, const morph_rle_t &src, const MaskRunsArg &m,
                        const MaskRunsArg &reflected, void *ws, hipStream_t s);

@@ -681,6 +681,41 @@ __global__ __launch_bounds__(256) void mask_kernel(MaskPage P, MaskRunsArg M, lo
     }
 }
 
+
+// ---------------------------------------------------------------- line shifts
+// Every line moves right by its own shift (section "Scaling, Skewing, and
+// Rotation": skews are shifts within lines): dst(x, y) = src(x - shift[y], y)
+// inside the source, fill elsewhere.  One thread per output word: the two
+// source words under it, a funnel shift, then the fill outside the source
+// and 0 in the destination's pad bits.
+__global__ __launch_bounds__(256) void shift_rows_kernel(const uint64_t *__restrict__ src, int Ws, int nws, int sstride,
+                                                         uint64_t *__restrict__ dst, int Wd, int nwd, int dstride,
+                                                         const int *__restrict__ shifts, int fill, long long total)
+{
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total) return;
+    const long long r = t / nwd;
+    const int j = (int)(t - r * nwd);
+    const long long sh = min(max((long long)shifts[r], -(1LL << 30)), 1LL << 30);
+    const uint64_t fw = fill ? kOnes : 0ull;
+    const uint64_t *row = src + r * sstride;
+    const long long p = 64LL * j - sh;      // source bit under the word's bit 0
+    const long long q = p >> 6;             // floor
+    const int b = (int)(p & 63);
+    auto word = [&](long long k) { return (k >= 0 && k < nws) ? row[k] : fw; };
+    const uint64_t lo = word(q);
+    const uint64_t v = b == 0 ? lo : funnel_r(word(q + 1), lo, b);
+    // bits of the word whose source lies in [0, Ws)
+    const long long x0 = 64LL * j;
+    const long long a = max(sh, x0) - x0, e = min(sh + Ws, x0 + 64) - x0;
+    uint64_t valid = 0;
+    if (a < e) valid = (~0ull >> (64 - (e - a))) << a;
+    uint64_t o = (v & valid) | (fw & ~valid);
+    const int rem = Wd - 64 * j;            // pad bits of the destination
+    if (rem < 64) o &= (1ull << rem) - 1;
+    dst[r * dstride + j] = o;
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -889,6 +924,22 @@ hipError_t launch_mask(const MaskPage &p, const MaskRunsArg &m, int npages, hipS
     trace_before(MORPH_K_MASK, stream);
     hipLaunchKernelGGL(mask_kernel, dim3((unsigned)ntiles), dim3(256), lds, stream, p, m, ntiles);
     trace_after(MORPH_K_MASK, stream, 16.0 * p.nw * (double)p.H * npages);
+    return hipGetLastError();
+}
+
+hipError_t shift_rows_packed(const morph_bitmap_t &dst, const morph_bitmap_t &src, const int *shifts, int fill,
+                             hipStream_t stream)
+{
+    const long long R = (long long)src.height * src.npages;
+    const int nws = (src.width + 63) / 64, nwd = (dst.width + 63) / 64;
+    const long long total = R * nwd;
+    if (total <= 0) return hipSuccess;
+    if ((total + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
+    trace_before(MORPH_K_SHIFT, stream);
+    hipLaunchKernelGGL(shift_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, src.words,
+                       src.width, nws, src.stride_words, dst.words, dst.width, nwd, dst.stride_words, shifts, fill,
+                       total);
+    trace_after(MORPH_K_SHIFT, stream, 8.0 * R * ((double)nws + nwd) + 4.0 * R);
     return hipGetLastError();
 }
 

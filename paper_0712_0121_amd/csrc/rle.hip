@@ -1027,6 +1027,76 @@ __global__ __launch_bounds__(256) void mask_and_kernel(RowsIn src, int P, int H,
     }
 }
 
+// ---------------------------------------------------------- line shifts, runs
+// Every line moves right by its own shift: its runs move, are cut to the
+// destination width and, with fill, the pixels that come from outside the
+// source line are 1 (a run touching a source border then reaches out to
+// the destination's edge).  Two passes with one group per row: counts,
+// then the runs at scanned offsets.
+__device__ __forceinline__ int shift_ncand(const int2 *R, int n, int Ws, int fill)
+{
+    if (!fill) return n;
+    return n + ((n == 0 || R[0].x != 0) ? 1 : 0) + ((n == 0 || R[n - 1].y != Ws) ? 1 : 0);
+}
+
+__device__ __forceinline__ int2 shift_cand(const int2 *R, int n, int Ws, int Wd, int fill, long long sh, int k)
+{
+    long long s, e;
+    if (!fill) {
+        s = R[k].x;
+        e = R[k].y;
+    } else {
+        const int i = k - ((n == 0 || R[0].x != 0) ? 1 : 0);
+        if (i < 0) {
+            s = -(1LL << 40);
+            e = 0;
+        } else if (i == n) {
+            s = Ws;
+            e = 1LL << 40;
+        } else {
+            s = R[i].x == 0 ? -(1LL << 40) : R[i].x;
+            e = R[i].y == Ws ? (1LL << 40) : R[i].y;
+        }
+    }
+    return make_int2((int)max(0LL, s + sh), (int)min((long long)Wd, e + sh));
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(256) void shift_rows_rle_kernel(RowsIn src, long long R, int Ws, int Wd,
+                                                             const int *__restrict__ shifts, int fill,
+                                                             int *__restrict__ counts, const int *__restrict__ out_rp,
+                                                             int *__restrict__ out_runs, long long cap,
+                                                             unsigned long long *trace)
+{
+    const long long r = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (r >= R) return;                     // whole group
+    const int gl = glane();
+    long long base;
+    int n;
+    row_span(src, r, base, n);
+    const int2 *Rw = reinterpret_cast<const int2 *>(src.runs) + base;
+    const long long sh = min(max((long long)shifts[r], -(1LL << 30)), 1LL << 30);
+    const int nc = shift_ncand(Rw, n, Ws, fill);
+    long long o = EMIT ? out_rp[r] : 0;
+    int carry = 0;
+    for (int k0 = 0; k0 < nc; k0 += kGroup) {
+        const int k = k0 + gl;
+        int2 c = make_int2(0, 0);
+        if (k < nc) c = shift_cand(Rw, n, Ws, Wd, fill, sh, k);
+        const int l = live(c) ? 1 : 0;
+        const int inc = group_incl_scan(l);
+        if (EMIT && l) {
+            const long long idx = o + carry + inc - l;
+            if (idx < cap) reinterpret_cast<int2 *>(out_runs)[idx] = c;
+        }
+        carry += group_last(inc);
+    }
+    if (gl == 0) {
+        if (!EMIT) counts[r] = carry;
+        if (EMIT && trace) trace_add(trace, (unsigned long long)n, (unsigned long long)carry);
+    }
+}
+
 // Canonical-form check: sets *bad when a row breaks it.
 __global__ __launch_bounds__(256) void validate_kernel(const int *__restrict__ rp,
                                                        const int *__restrict__ runs, int R, int W,
@@ -1383,6 +1453,28 @@ hipError_t rle_mask_op(int op, const morph_rle_t &dst, const morph_rle_t &src, c
         return e != hipSuccess ? e : fin(b, 0);
     }
     return hipErrorInvalidValue;
+}
+
+size_t shift_rows_rle_workspace(long long R) { return r256((size_t)R * 4) + scan_workspace(R); }
+
+hipError_t shift_rows_rle(const morph_rle_t &dst, const morph_rle_t &src, const int *shifts, int fill, void *ws,
+                          hipStream_t s)
+{
+    const long long R = (long long)src.height * src.npages;
+    int *counts = (int *)ws;
+    int *tmp = (int *)((char *)ws + r256((size_t)R * 4));
+    const RowsIn in{src.row_ptr, nullptr, src.runs, (long long)src.capacity};
+    const dim3 grid(blocks_for(R, kGroupsPerBlock));
+    unsigned long long *tr = trace_counters();
+    trace_before(MORPH_K_SHIFT_RLE, s);
+    hipLaunchKernelGGL(shift_rows_rle_kernel<false>, grid, dim3(256), 0, s, in, R, src.width, dst.width, shifts, fill,
+                       counts, nullptr, nullptr, 0LL, nullptr);
+    hipError_t e = exclusive_scan(counts, (int)R, dst.row_ptr, tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(shift_rows_rle_kernel<true>, grid, dim3(256), 0, s, in, R, src.width, dst.width, shifts, fill,
+                       nullptr, dst.row_ptr, dst.runs, (long long)dst.capacity, trace_block(tr, MORPH_K_SHIFT_RLE));
+    trace_after(MORPH_K_SHIFT_RLE, s, 8.0 * R + 4.0 * (R + 1));
+    return hipGetLastError();
 }
 
 int rle_validate(const morph_rle_t &r, hipStream_t s, hipError_t *err)

@@ -282,3 +282,22 @@ def test_mask_argument_errors():
     assert MR(0, rle(a, W, H, cap - 1), rle(b, W, H, cap), mk) == -6
     assert MR(0, rle(a, W, H, cap), rle(b, W, H, cap), mk) == -4
     assert MR(0, rle(a, W, H, cap), rle(b, W, H, cap), too_many) == -8
+
+
+def test_shift_argument_errors():
+    a, b, c = HostBuf(1 << 16), HostBuf(1 << 16), HostBuf(1 << 12)
+    SP = lambda d, s, sh=c.ptr, fill=0: M._lib.morph_shift_rows_packed(ctypes.byref(d), ctypes.byref(s), sh, fill, None)
+    assert SP(bitmap(a, 120, 10), bitmap(b, 100, 10), None) == -1
+    assert SP(bitmap(a, 120, 10), bitmap(b, 100, 10), c.ptr + 2) == -1
+    assert SP(bitmap(a, 120, 10), bitmap(b, 100, 10), fill=2) == -1
+    assert SP(bitmap(a, 120, 11), bitmap(b, 100, 10)) == -2
+    assert SP(bitmap(a, 120, 10), bitmap(a, 100, 10)) == -3
+    W, H = 100, 10
+    SR = lambda d, s, ws=None, n=0: M._lib.morph_shift_rows_rle(ctypes.byref(d), ctypes.byref(s), c.ptr, 1, ws, n, None)
+    capd = M.morph_rle_max_runs(150, H)
+    assert SR(rle(a, 150, H + 1, capd), rle(b, W, H, 10)) == -2
+    assert SR(rle(a, 150, H, capd - 1), rle(b, W, H, 10)) == -6
+    assert SR(rle(a, 150, H, capd), rle(a, W, H, 10)) == -3
+    assert SR(rle(a, 150, H, capd), rle(b, W, H, 10)) == -4
+    need = M.morph_shift_rows_rle_workspace_bytes(H)
+    assert need >= H * 4
