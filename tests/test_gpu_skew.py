@@ -103,7 +103,7 @@ def test_rotation_matches_oracle(angle):
 @pytest.mark.parametrize("slope", [(0, 1), (1, 1), (-1, 1), (1, 3), (-2, 5), (7, 8)], ids=lambda s: "%d_%d" % s)
 def test_line_ops_match_oracle(op, slope):
     num, den = slope
-    img = blobs_img(num * 3 + den, 70, 150, 0.5)
+    img = blobs_img(abs(num) * 3 + den + 10, 70, 150, 0.5)
     pk, rl = both(img)
     for length in (3, 8, 15):
         want = osh.line_op(op, img, length, num, den)
