@@ -148,8 +148,10 @@ int morph_close_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src
  * dst->capacity must be at least morph_rle_max_runs(width, height*npages)
  * (MORPH_E_CAPACITY otherwise).  ws: at least morph_rle_workspace_bytes(op,
  * width, height, npages, se) bytes.  Images whose worst case,
- * npages*(height+h-1)*ceil(width/2) runs, reaches 2^31 give
- * MORPH_E_UNSUPPORTED.
+ * npages*height*ceil(width/2) runs, or whose npages*(height+h-1) extended
+ * rows (twice that for elements of 9 or more rows and 2 or more columns,
+ * whose between-line pass may keep two rows per extended row), reach 2^31
+ * give MORPH_E_UNSUPPORTED.
  */
 int morph_erode_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
                          void *ws, size_t ws_bytes, morph_stream_t stream);
@@ -405,7 +407,8 @@ enum {
     MORPH_K_MASK_RLE = 13,     /* intersection with one eroded, shifted mask run on runs */
     MORPH_K_SHIFT = 14,        /* packed line shifts */
     MORPH_K_SHIFT_RLE = 15,    /* line shifts on runs (count and emit launches) */
-    MORPH_K_COUNT = 16
+    MORPH_K_COL_SCAN = 16,     /* between-line block prefix scans on runs (tall elements) */
+    MORPH_K_COUNT = 17
 };
 typedef struct {
     int64_t launches;

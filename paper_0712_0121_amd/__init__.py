@@ -88,7 +88,7 @@ class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 16
+MORPH_K_COUNT = 17
 
 
 class morph_page_desc_t(ctypes.Structure):

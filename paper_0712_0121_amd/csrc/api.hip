@@ -515,8 +515,12 @@ static int rect_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, morp
     if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
         return MORPH_E_SHAPE;
     if (rle_alias(dst, src)) return MORPH_E_ALIAS;
-    const long long ext = (long long)src->npages * (src->height + (long long)se.h - 1);
-    if (ext * ((((long long)src->width + 1) / 2 + 15) & ~15LL) >= 0x7fffffffLL) return MORPH_E_UNSUPPORTED;
+    // slot rows are indexed in 32 bits (their runs in 64); the result's row
+    // offsets are int32
+    const long long ext = (long long)src->npages * (src->height + (long long)se.h - 1) * (rle_uses_scan(se) ? 2 : 1);
+    if (ext >= 0x7fffffffLL ||
+        (long long)src->npages * src->height * (((long long)src->width + 1) / 2) >= 0x7fffffffLL)
+        return MORPH_E_UNSUPPORTED;
     if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
     const size_t need = rle_op_workspace(op, src->width, src->height * src->npages, src->height, se);
     if (!ws || ws_bytes < need) return MORPH_E_WORKSPACE;
@@ -1078,7 +1082,8 @@ const char *morph_kernel_name(int k)
                                                "pack_rows_kernel", "transpose_kernel",
                                                "decode_transpose_kernel", "components",
                                                "component_stats_kernel", "run_hist_kernel", "mask_kernel",
-                                               "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel"};
+                                               "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel",
+                                               "col_scan_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

@@ -827,6 +827,137 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     }
 }
 
+// ----------------------------------------------------- block prefix scans
+// Between-line erosion by h rows in two launches for tall elements: the
+// extended rows 0 .. NA-1 of a page (row x = stored row x - off, a full
+// row outside) fall into blocks of h rows; one group per block walks it
+// down, writing G(x) = E(x0) AND ... AND E(x), and one walks it up,
+// writing F(x) = E(x) AND ... AND E(x1 - 1), E being the row after the
+// within-line pass (ROWX).  Output row y is then F(y) AND G(y + h - 1):
+// the two ranges meet to cover y .. y + h - 1 (when y starts a block,
+// G(y + h - 1) is the whole block, which F(y) already is).  F(x) is
+// stored at row x and G(x) at row NA + x of a page of 2 NA slot rows, so
+// the combining step is col_and_kernel<false> with K = NA + h - 1.
+// The current row of a walk stays in the group's LDS window (global
+// memory, behind a fence, when it has more than kStageRuns runs).
+template <bool ROWX>
+__global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int real, int NA, int h, int nblk, int P,
+                                                       int W, RowX x, int *__restrict__ out_cnt,
+                                                       int *__restrict__ out_runs, long long cap_row,
+                                                       unsigned long long *trace)
+{
+    __shared__ int2 win[kGroupsPerBlock][2][kStageRuns];
+    const long long t = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
+    if (t >= (long long)P * nblk * 2) return;        // whole group
+    const int gl = glane();
+    const int dir = (int)(t & 1);                    // 0: down (G), 1: up (F)
+    const long long pb = t >> 1;
+    const int page = (int)(pb / nblk), blk = (int)(pb - (long long)page * nblk);
+    const int x0 = blk * h, x1 = min(x0 + h, NA);
+    const int extra = (ROWX && x.comp) ? 1 : 0;
+    int2 *wa = win[threadIdx.x >> 4][0], *wb = win[threadIdx.x >> 4][1];
+    const int2 *cur = wa;                            // the current row: LDS window or a stored output row
+    int ncur = 0;
+    unsigned long long rin = 0, rout = 0;
+    for (int s = 0; s < x1 - x0; s++) {
+        const int xr = dir == 0 ? x0 + s : x1 - 1 - s;
+        const long long orow = (long long)page * 2 * NA + (dir == 0 ? NA + xr : xr);
+        int2 *o = reinterpret_cast<int2 *>(out_runs) + orow * cap_row;
+        const int ir = xr - off;
+        const bool stored = ir >= 0 && ir < real;
+        long long base = 0;
+        int n = 0;
+        if (stored) row_span(in, (long long)page * real + ir, base, n);
+        const int *R = in.runs + 2 * base;
+        if (dir == 0) rin += n;
+        int cnt = 0;
+        if (s == 0 || (s > 0 && ncur > 0 && !stored)) {
+            // the row itself (first step), or the current row unchanged (a full row meets it)
+            if (s == 0 && !stored) {
+                if (gl == 0) {
+                    o[0] = make_int2(0, W);
+                    wb[0] = make_int2(0, W);
+                }
+                cnt = 1;
+            } else if (s == 0) {
+                const int nc = n + extra;
+                for (int k0 = 0; k0 < nc; k0 += kGroup) {
+                    const int k = k0 + gl;
+                    const int2 c = k < nc ? cand<ROWX>(x, R, n, k) : make_int2(0, 0);
+                    const bool keep = k < nc && live(c);
+                    const unsigned gm = group_ballot(keep);
+                    const int idx = cnt + __popc(gm & ((1u << gl) - 1));
+                    if (keep && idx < cap_row) {
+                        o[idx] = c;
+                        if (idx < kStageRuns) wb[idx] = c;
+                    }
+                    cnt += __popc(gm);
+                }
+            } else {
+                for (int k = gl; k < ncur; k += kGroup) {
+                    const int2 c = cur[k];
+                    o[k] = c;
+                    if (k < kStageRuns) wb[k] = c;
+                }
+                cnt = ncur;
+            }
+        } else if (ncur > 0) {
+            // cur AND the candidates of the row: lanes over the row's candidates
+            const int nc = n + extra;
+            int carry = 0;
+            for (int k0 = 0; k0 < nc; k0 += kGroup) {
+                const int k = k0 + gl;
+                int c = 0, span = 0, j0 = 0, sa = 0, ea = 0;
+                if (k < nc) {
+                    const int2 a = cand<ROWX>(x, R, n, k);
+                    sa = a.x;
+                    ea = a.y;
+                }
+                if (k < nc && sa < ea) {
+                    int lo = 0, hi = ncur;           // the first run of cur that ends after sa
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (cur[mid].y > sa) hi = mid; else lo = mid + 1;
+                    }
+                    j0 = lo;
+                    for (int j = j0; j < ncur && cur[j].x < ea; j++) span++;
+                    c = span;
+                }
+                const int inc = group_incl_scan(c);
+                int idx = carry + inc - c;
+                for (int j = j0; j < j0 + span; j++) {
+                    const int2 b = cur[j];
+                    const int2 v = make_int2(max(sa, b.x), min(ea, b.y));
+                    if (idx < cap_row) {
+                        o[idx] = v;
+                        if (idx < kStageRuns) wb[idx] = v;
+                    }
+                    idx++;
+                }
+                carry += group_last(inc);
+            }
+            cnt = carry;
+        }
+        cnt = (int)min((long long)cnt, cap_row);
+        if (gl == 0) out_cnt[orow] = cnt;
+        rout += cnt;
+        // the new row becomes the current one
+        if (cnt <= kStageRuns) {
+            wave_lds_sync();
+            int2 *tmp = wa;
+            wa = wb;
+            wb = tmp;
+            cur = wa;
+        } else {
+            __threadfence();
+            __builtin_amdgcn_wave_barrier();
+            cur = o;
+        }
+        ncur = cnt;
+    }
+    if (trace && gl == 0) trace_add(trace, rin, rout);
+}
+
 // ---------------------------------------------------------- final packing
 // Runs per row of the complement of slot rows: the gaps, without an empty
 // first or last one.
@@ -1214,11 +1345,19 @@ struct RleWs {
     size_t bytes;
 };
 
+// Elements at least this tall (and wider than a column) may run between
+// lines as block prefix scans (two launches) instead of the doubling steps
+// (one launch per offset).
+constexpr int kScanMinH = 9;
+
+bool rle_uses_scan(morph_se_t se) { return se.h >= kScanMinH && se.w > 1; }
+
 static RleWs rle_layout(void *base, int32_t W, int32_t rows, int32_t H, morph_se_t se)
 {
     const long long P = rows / H;
     RleWs L{};
-    L.rows_max = P * (H + (long long)se.h - 1);
+    // the scans keep 2 (H + h - 1) rows per page
+    L.rows_max = P * (H + (long long)se.h - 1) * (rle_uses_scan(se) ? 2 : 1);
     L.cap_row = ((W + 1) / 2 + 15) & ~15LL;      // slot rows start on 128-byte lines
     char *p = (char *)base;
     size_t off = 0;
@@ -1252,7 +1391,7 @@ static RowsIn slot_rows(const RleWs &L, int i)
 // the P*H result rows.  `in` may be the other slot buffer, never `to`.
 static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w, int h, int cx, int cy,
                        const RleWs &L, int to, hipStream_t s, hipError_t *err, int *gap_out = nullptr,
-                       bool *gaps_done = nullptr)
+                       bool *gaps_done = nullptr, bool scan = false)
 {
     if (gaps_done) *gaps_done = false;
     const int R = P * H;
@@ -1265,6 +1404,24 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
         trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
         *err = hipGetLastError();
         return to;
+    }
+    const RowX xs{cx, w - 1 - cx, comp_in, W};
+    if (scan && rle_uses_scan(morph_se_t{w, h, cx, cy})) {
+        const int NA = H + h - 1, nblk = (NA + h - 1) / h;
+        trace_before(MORPH_K_COL_SCAN, s);
+        hipLaunchKernelGGL(col_scan_kernel<true>, dim3(blocks_for((long long)P * nblk * 2, kGroupsPerBlock)),
+                           dim3(256), 0, s, in, cy, H, NA, h, nblk, P, W, xs, L.cnt[to], L.runs[to],
+                           (long long)L.cap_row, trace_block(tr, MORPH_K_COL_SCAN));
+        trace_after(MORPH_K_COL_SCAN, s, 4.0 * P * ((double)H + 2.0 * NA));
+        const int fin = 1 - to;
+        trace_before(MORPH_K_COL_AND, s);
+        hipLaunchKernelGGL(col_and_kernel<false>, dim3(blocks_for((long long)P * H, kGroupsPerBlock)), dim3(256), 0, s,
+                           slot_rows(L, to), 0, 2 * NA, 2 * NA, NA + h - 1, P, W, xs, L.cnt[fin], L.runs[fin],
+                           (long long)L.cap_row, gap_out, trace_block(tr, MORPH_K_COL_AND));
+        trace_after(MORPH_K_COL_AND, s, 4.0 * P * (2.0 * NA + H));
+        if (gap_out && gaps_done) *gaps_done = true;
+        *err = hipGetLastError();
+        return fin;
     }
     // rows of the extended page: 0 .. H+h-2, row x being image row x - cy
     int off = cy, real = H, NA = H + h - 1;
@@ -1337,22 +1494,30 @@ hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, m
     hipError_t e = hipSuccess;
     bool g = false;                 // the complement's counts came with the last step
     int b;
+    // The block scans pay off where the rows they intersect thin out: the
+    // erosion of the image by an element wider than a column, and the second
+    // chain of an opening or closing by one (the complement of an eroded or
+    // dilated image has few runs).  Eroding the complement of the image
+    // itself keeps its long white runs through every step, and a single
+    // column leaves the rows as they are; there the doubling steps are
+    // faster (measured on the letter batch).
+    const bool wide = w > 1;
     switch (op) {
     case MORPH_ERODE:
-        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
+        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e, nullptr, nullptr, wide);
         return e != hipSuccess ? e : finish(L, b, 0, dst, W, s, false);
     case MORPH_DILATE:
         b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e, L.fcount, &g);
         return e != hipSuccess ? e : finish(L, b, 1, dst, W, s, g);
     case MORPH_OPEN:
-        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e);
+        b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e, nullptr, nullptr, wide);
         if (e != hipSuccess) return e;
-        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, rx, ry, L, 1 - b, s, &e, L.fcount, &g);
+        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, rx, ry, L, 1 - b, s, &e, L.fcount, &g, wide);
         return e != hipSuccess ? e : finish(L, b, 1, dst, W, s, g);
     case MORPH_CLOSE:
         b = erode_chain(in, 1, P, W, H, w, h, rx, ry, L, 0, s, &e);
         if (e != hipSuccess) return e;
-        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, cx, cy, L, 1 - b, s, &e);
+        b = erode_chain(slot_rows(L, b), 1, P, W, H, w, h, cx, cy, L, 1 - b, s, &e, nullptr, nullptr, wide);
         return e != hipSuccess ? e : finish(L, b, 0, dst, W, s, false);
     }
     return hipErrorInvalidValue;

@@ -231,12 +231,14 @@ def test_letter_batch_as_timed(op):
 
 
 @pytest.mark.parametrize("op", pagegen.OPS)
-@pytest.mark.parametrize("se", [(3, 5, 1, 2), (1, 9, 0, 4), (6, 4, 5, 0)])
+@pytest.mark.parametrize("se", [(3, 5, 1, 2), (1, 9, 0, 4), (6, 4, 5, 0), (3, 11, 1, 5), (2, 17, 0, 16)])
 def test_rle_long_rows(op, se):
     """Rows of several hundred runs (more than a group keeps in registers or
     LDS), so the within-line pass, every column step (the first one with
     the within-line erosion applied as rows are read) and the final packing
-    take their global-memory paths; one page mixes long rows with short."""
+    take their global-memory paths (for tall elements, the block scans keep
+    their running rows in global memory); one page mixes long rows with
+    short."""
     W, H = 1500, 60
     r = np.random.default_rng(11)
     img = (r.random((H, W)) < 0.5).astype(np.uint8)
@@ -254,5 +256,5 @@ def test_rle_alternating_rows_all_ops():
     img = np.tile((np.arange(W) % 2 == 0).astype(np.uint8), (H, 1))
     img[::3] ^= 1
     for op in pagegen.OPS:
-        for se in [(2, 2, 0, 1), (1, 5, 0, 2), (3, 1, 1, 0)]:
+        for se in [(2, 2, 0, 1), (1, 5, 0, 2), (3, 1, 1, 0), (2, 10, 1, 3)]:
             assert_rle_equal(rle_op(op, img, se), oracle.apply(op, img, se), "%s %s" % (op, se))
