@@ -839,14 +839,16 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
 // stored at row x and G(x) at row NA + x of a page of 2 NA slot rows, so
 // the combining step is col_and_kernel<false> with K = NA + h - 1.
 // The current row of a walk stays in the group's LDS window (global
-// memory, behind a fence, when it has more than kStageRuns runs).
+// memory, behind a fence, when it has more than kScanWin runs).
+constexpr int kScanWin = 64;             // runs of the current row a group keeps in LDS (16 KiB a workgroup)
+
 template <bool ROWX>
 __global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int real, int NA, int h, int nblk, int P,
                                                        int W, RowX x, int *__restrict__ out_cnt,
                                                        int *__restrict__ out_runs, long long cap_row,
                                                        unsigned long long *trace)
 {
-    __shared__ int2 win[kGroupsPerBlock][2][kStageRuns];
+    __shared__ int2 win[kGroupsPerBlock][2][kScanWin];
     const long long t = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (t >= (long long)P * nblk * 2) return;        // whole group
     const int gl = glane();
@@ -889,7 +891,7 @@ __global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int r
                     const int idx = cnt + __popc(gm & ((1u << gl) - 1));
                     if (keep && idx < cap_row) {
                         o[idx] = c;
-                        if (idx < kStageRuns) wb[idx] = c;
+                        if (idx < kScanWin) wb[idx] = c;
                     }
                     cnt += __popc(gm);
                 }
@@ -897,7 +899,7 @@ __global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int r
                 for (int k = gl; k < ncur; k += kGroup) {
                     const int2 c = cur[k];
                     o[k] = c;
-                    if (k < kStageRuns) wb[k] = c;
+                    if (k < kScanWin) wb[k] = c;
                 }
                 cnt = ncur;
             }
@@ -930,7 +932,7 @@ __global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int r
                     const int2 v = make_int2(max(sa, b.x), min(ea, b.y));
                     if (idx < cap_row) {
                         o[idx] = v;
-                        if (idx < kStageRuns) wb[idx] = v;
+                        if (idx < kScanWin) wb[idx] = v;
                     }
                     idx++;
                 }
@@ -942,7 +944,7 @@ __global__ __launch_bounds__(256) void col_scan_kernel(RowsIn in, int off, int r
         if (gl == 0) out_cnt[orow] = cnt;
         rout += cnt;
         // the new row becomes the current one
-        if (cnt <= kStageRuns) {
+        if (cnt <= kScanWin) {
             wave_lds_sync();
             int2 *tmp = wa;
             wa = wb;
