@@ -1351,6 +1351,9 @@ struct RleWs {
 // lines as block prefix scans (two launches) instead of the doubling steps
 // (one launch per offset).
 constexpr int kScanMinH = 9;
+// ... and only over stacks of at least this many rows: a walk is h steps
+// long, so on a few pages the doubling steps finish sooner.
+constexpr long long kScanMinRows = 32768;
 
 bool rle_uses_scan(morph_se_t se) { return se.h >= kScanMinH && se.w > 1; }
 
@@ -1408,7 +1411,7 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
         return to;
     }
     const RowX xs{cx, w - 1 - cx, comp_in, W};
-    if (scan && rle_uses_scan(morph_se_t{w, h, cx, cy})) {
+    if (scan && rle_uses_scan(morph_se_t{w, h, cx, cy}) && (long long)P * H >= kScanMinRows) {
         const int NA = H + h - 1, nblk = (NA + h - 1) / h;
         trace_before(MORPH_K_COL_SCAN, s);
         hipLaunchKernelGGL(col_scan_kernel<true>, dim3(blocks_for((long long)P * nblk * 2, kGroupsPerBlock)),

@@ -258,3 +258,32 @@ def test_rle_alternating_rows_all_ops():
     for op in pagegen.OPS:
         for se in [(2, 2, 0, 1), (1, 5, 0, 2), (3, 1, 1, 0), (2, 10, 1, 3)]:
             assert_rle_equal(rle_op(op, img, se), oracle.apply(op, img, se), "%s %s" % (op, se))
+
+
+@pytest.mark.parametrize("op", pagegen.OPS)
+def test_rle_block_scans_on_large_stacks(op):
+    """Stacks of at least 32768 rows take the block-scan between-line pass
+    for elements of 9 or more rows and 2 or more columns: 560 copies of a
+    page whose rows hold several hundred runs (the scans' running rows then
+    live in global memory), and 12 letter pages."""
+    W, H, P = 1500, 60, 560
+    r = np.random.default_rng(13)
+    img = (r.random((H, W)) < 0.5).astype(np.uint8)
+    img[40:45] = 0
+    img[40:45, 100:400] = 1
+    for se in [(3, 11, 1, 5), (2, 17, 0, 16)]:
+        want = oracle.apply(op, img, se)
+        out = rle_op(op, np.tile(img, (P, 1)), se, npages=P)
+        rp, runs = out.to_host()
+        wrp, wruns = oracle.rle_encode(want)
+        n1 = int(wrp[-1])
+        assert int(rp[-1]) == P * n1, "%s %s" % (op, se)
+        counts = np.diff(rp).reshape(P, H)
+        np.testing.assert_array_equal(counts, np.tile(np.diff(wrp), (P, 1)), err_msg="%s %s" % (op, se))
+        np.testing.assert_array_equal(runs.reshape(P, n1, 2), np.tile(wruns.reshape(1, n1, 2), (P, 1, 1)),
+                                      err_msg="%s %s" % (op, se))
+    pages = [pagegen.letter_page(2100 + i).img for i in range(12)]
+    stack = np.concatenate(pages)
+    for se in [(21, 21, 10, 10), (9, 51, 4, 25)]:
+        out = rle_op(op, stack, se, npages=12)
+        assert_rle_equal(out, np.concatenate([oracle.sat_apply(op, p, se) for p in pages]), "%s %s" % (op, se))
