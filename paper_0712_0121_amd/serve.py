@@ -43,7 +43,7 @@ def chain_ses(chain):
     return [(op, centred(*wh)) if len(wh) == 2 else (op, tuple(wh)) for op, wh in chain]
 
 
-@dataclasses.dataclass(eq=False)
+@dataclasses.dataclass(eq=False, slots=True)
 class Request:
     rid: int
     W: int
@@ -228,6 +228,13 @@ class GpuExecutor:
         # (Server(keep_results=False)), since a kept result is a view of one
         self.recycle = recycle_outputs
         self.out_pool = collections.defaultdict(list)
+        # device buffer pairs per page shape, each with its batch descriptors
+        # per chain; a pair goes back on release once the request's download
+        # has completed (every upload, launch and copy on it is then done), so
+        # the buffers need no per-stream use records, whose bookkeeping on
+        # every allocation and free costs more host time than the page's
+        # launches
+        self.buf_pool = collections.defaultdict(list)
 
     def footprint(self, r: Request) -> int:
         return 2 * r.H * ((r.W + 63) // 64) * 8
@@ -237,12 +244,13 @@ class GpuExecutor:
         host = r.words
         if not isinstance(host, torch.Tensor):
             host = torch.from_numpy(np.ascontiguousarray(host).view(np.int64))
-        a = M.Bitmap.empty(r.W, r.H, device=self.device)
-        b = M.Bitmap.empty(r.W, r.H, device=self.device)
-        for t in (a.words, b.words):           # used on the side streams
-            t.record_stream(self.copy)
-            t.record_stream(self.compute)
-            t.record_stream(self.down)
+        pool = self.buf_pool[(r.W, r.H)]
+        if pool:
+            a, b, cache = pool.pop()
+        else:
+            a = M.Bitmap.empty(r.W, r.H, device=self.device)
+            b = M.Bitmap.empty(r.W, r.H, device=self.device)
+            cache = {}
         # a request alone on the device has nothing to overlap with: its
         # copies go on the compute stream, which saves two cross-stream waits
         up = self.compute if r.alone else self.copy
@@ -254,9 +262,13 @@ class GpuExecutor:
                 ev.record(up)
         # the chain's batch descriptors, built once: operation k reads the
         # buffer written by operation k-1
-        bufs = (a, b)
-        descs = [M.page_desc(bufs[(k + 1) % 2], bufs[k % 2], op, se) for k, (op, se) in enumerate(r.chain)]
-        r.state = {"cur": a, "nxt": b, "up": ev, "host": host, "descs": descs}
+        key = tuple(r.chain)
+        descs = cache.get(key)
+        if descs is None:
+            bufs = (a, b)
+            descs = [M.page_desc(bufs[(k + 1) % 2], bufs[k % 2], op, se) for k, (op, se) in enumerate(r.chain)]
+            cache[key] = descs
+        r.state = {"cur": a, "nxt": b, "pair": (a, b, cache), "up": ev, "host": host, "descs": descs}
 
     def launch(self, reqs):
         torch, M = self.torch, self.M
@@ -321,9 +333,22 @@ class GpuExecutor:
         return r.state["out"].numpy().view(np.uint64)
 
     def release(self, r: Request):
-        out, down = r.state.get("out"), r.state.get("down")
-        if self.recycle and out is not None and down is not None and down.query():
+        st = r.state
+        out, down, pair = st.get("out"), st.get("down"), st.get("pair")
+        finished = down is not None and down.query()
+        if self.recycle and out is not None and finished:
             self.out_pool[tuple(out.shape)].append(out)
+        if pair is not None:
+            if finished:
+                self.buf_pool[(r.W, r.H)].append(pair)
+            else:
+                # a failed request may still have work queued on the side
+                # streams: the allocator must not hand the buffers out again
+                # before that work is done
+                for t in (pair[0].words, pair[1].words):
+                    t.record_stream(self.copy)
+                    t.record_stream(self.compute)
+                    t.record_stream(self.down)
         r.state = {}
 
 
