@@ -73,9 +73,12 @@ struct Launch {
 // With small_tiles, a one-stage launch whose halo rows stay under a fifth
 // of a small tile runs four 256-thread workgroups per CU instead of two
 // 512-thread ones (measured a few percent faster for short elements; the
-// number of launches does not change).
+// number of launches does not change).  With by_halo (single operations and
+// their workspace query, not batch pages, which need one launch each), two
+// stages whose halo rows outnumber a fused tile's rows run as two launches.
 static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int tile_rows,
-                          int strip_words, std::vector<Launch> &out, bool small_tiles = false)
+                          int strip_words, std::vector<Launch> &out, bool small_tiles = false,
+                          bool by_halo = false)
 {
     const std::vector<Pass> ps = op_passes(op, se);
     const int nw = (W + 63) / 64;
@@ -94,7 +97,21 @@ static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int t
             p.st[0] = ps[i].st;
             p.st[1] = ps[i + 1].st;
             RectPage q = p;
-            if (plan_tiles(q, tile_rows, strip_words, npages) && q.TR >= 8) {
+            bool share = plan_tiles(q, tile_rows, strip_words, npages) && q.TR >= 8;
+            if (share && by_halo) {
+                // two stages share a tile only while their halo rows
+                // (h1 - 1 + h2 - 1) do not outnumber the most output rows
+                // such a tile can hold (page count aside, so that the
+                // workspace query plans the same launches): beyond that the
+                // first stage recomputes more rows than two single-stage
+                // launches cost with the intermediate's round trip through
+                // HBM (51 x 51 opening of letter pages: fused tiles of 76
+                // rows under 100 halo rows, 0.57 ms; two launches 0.41 ms)
+                RectPage r = p;
+                const int hsum2 = ps[i].st.h - 1 + ps[i + 1].st.h - 1;
+                share = plan_tiles(r, 1 << 30, strip_words, npages) && hsum2 <= r.TR;
+            }
+            if (share) {
                 p = q;
                 fused = true;
             }
@@ -161,7 +178,7 @@ static int rect_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *
         return MORPH_E_SHAPE;
     if (overlap(dst->words, bitmap_extent(dst), src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
     std::vector<Launch> L;
-    if (!plan_launches(op, se, src->width, src->height, src->npages, 0, 0, L, true))
+    if (!plan_launches(op, se, src->width, src->height, src->npages, 0, 0, L, true, true))
         return MORPH_E_UNSUPPORTED;
     const int W = src->width, H = src->height, P = src->npages, nw = (W + 63) / 64;
     const size_t img = round256(image_bytes(W, H * P));
@@ -260,7 +277,7 @@ size_t morph_workspace_bytes(int op, int repr, int32_t width, int32_t height, mo
     if (width < 1 || height < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE) return 0;
     if (repr == MORPH_PACKED) {
         std::vector<Launch> L;
-        if (!plan_launches(op, se, width, height, 1, 0, 0, L)) return 0;
+        if (!plan_launches(op, se, width, height, 1, 0, 0, L, false, true)) return 0;
         const size_t img = round256(image_bytes(width, height));
         return L.size() <= 1 ? 0 : (L.size() == 2 ? img : 2 * img);
     }
