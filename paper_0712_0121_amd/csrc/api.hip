@@ -97,19 +97,23 @@ static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int t
             p.st[0] = ps[i].st;
             p.st[1] = ps[i + 1].st;
             RectPage q = p;
-            bool share = plan_tiles(q, tile_rows, strip_words, npages) && q.TR >= 8;
-            if (share && by_halo) {
-                // two stages share a tile only while their halo rows
-                // (h1 - 1 + h2 - 1) do not outnumber the most output rows
-                // such a tile can hold (page count aside, so that the
-                // workspace query plans the same launches): beyond that the
-                // first stage recomputes more rows than two single-stage
-                // launches cost with the intermediate's round trip through
-                // HBM (51 x 51 opening of letter pages: fused tiles of 76
-                // rows under 100 halo rows, 0.57 ms; two launches 0.41 ms)
+            bool share = plan_tiles(q, tile_rows, strip_words, npages);
+            if (share) {
+                // whether two stages share a tile depends on the element and
+                // the page width only, never on the page height: the
+                // workspace query sees a stack's total rows, the operation
+                // one page's.  r.TR is the most output rows a fused tile
+                // can hold.  With by_halo, the stages share a tile only
+                // while their halo rows (h1 - 1 + h2 - 1) do not outnumber
+                // those: beyond that the first stage recomputes more rows
+                // than two single-stage launches cost with the
+                // intermediate's round trip through HBM (51 x 51 opening of
+                // letter pages: fused tiles of 76 rows under 100 halo rows,
+                // 0.57 ms; two launches 0.41 ms)
                 RectPage r = p;
-                const int hsum2 = ps[i].st.h - 1 + ps[i + 1].st.h - 1;
-                share = plan_tiles(r, 1 << 30, strip_words, npages) && hsum2 <= r.TR;
+                r.H = 1 << 30;
+                share = plan_tiles(r, 1 << 30, strip_words, npages) && r.TR >= 8 &&
+                        (!by_halo || ps[i].st.h - 1 + ps[i + 1].st.h - 1 <= r.TR);
             }
             if (share) {
                 p = q;

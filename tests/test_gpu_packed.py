@@ -126,6 +126,27 @@ def test_stacked_pages_have_own_borders():
             np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("H", [1, 3, 7, 30, 80])
+def test_stacked_short_pages_fused_or_split(H):
+    """Openings and closings on stacks of short pages, with the workspace
+    sized from the stack's total rows as the binding does: whether the two
+    stages share a tile must not depend on the page height (pages under 8
+    rows, a 21 x 21 element whose 40 halo rows exceed 30-row pages, a
+    51 x 51 element split into two launches on any page)."""
+    W, P = 150, 6
+    imgs = [rnd_img(700 + 10 * H + k, H, W, 0.4) for k in range(P)]
+    img = np.concatenate(imgs, axis=0)
+    for op in ("open", "close"):
+        for se in [(3, 3, 1, 1), (21, 21, 10, 10), (51, 51, 25, 25), (2, 9, 1, 8)]:
+            got = run_packed(op, img, se, npages=P)
+            want = np.concatenate([expected_words(op, im, se) for im in imgs], axis=0)
+            np.testing.assert_array_equal(got, want, err_msg="%s %s H=%d" % (op, se, H))
+            src = M.Bitmap.from_words(oracle.pack(img), W, npages=P)
+            out = M.rect_packed(op, src, se)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.to_numpy(), want, err_msg="binding %s %s H=%d" % (op, se, H))
+
+
 # ------------------------------------------------------------ full letter page
 LETTER_SES = [(31, 1, 15, 0), (1, 31, 0, 15), (3, 3, 1, 1), (21, 21, 10, 10), (51, 51, 25, 25)]
 
