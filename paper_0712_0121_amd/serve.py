@@ -239,6 +239,13 @@ class GpuExecutor:
     def footprint(self, r: Request) -> int:
         return 2 * r.H * ((r.W + 63) // 64) * 8
 
+    def trim(self):
+        """Drops the pooled device buffer pairs and pinned result buffers,
+        for a server that has seen many page shapes.  Only idle buffers are
+        pooled, so this is safe at any time between steps."""
+        self.buf_pool.clear()
+        self.out_pool.clear()
+
     def begin(self, r: Request):
         torch, M = self.torch, self.M
         host = r.words

@@ -77,3 +77,38 @@ def test_small_budget_serves_everything():
     assert s.peak_used <= fp + 1
     for r in reqs:
         np.testing.assert_array_equal(r.result, expected(r))
+
+
+def test_pooled_buffers_across_traces():
+    """One executor serving three traces with its device buffer pairs and
+    pinned result buffers recycled (the benchmark's configuration, results
+    not kept), its pools dropped before the third: every result, taken as
+    it completes, equals the oracle's."""
+    from paper_0712_0121_amd.serve import GpuExecutor, Server, run_trace_served
+
+    class Capturing(GpuExecutor):
+        def __init__(self):
+            super().__init__(recycle_outputs=True)
+            self.got = {}
+
+        def finish(self, r):
+            res = super().finish(r)
+            self.got[r.rid] = res.copy()
+            return res
+
+    ex = Capturing()
+    for trace in range(3):
+        if trace == 2:
+            ex.trim()
+            assert not ex.buf_pool and not ex.out_pool
+        reqs = make_requests(15, seed=40 + trace)
+        for r in reqs:
+            r.rid += 100 * trace
+        arrivals = np.cumsum(np.random.default_rng(trace).exponential(0.0003, len(reqs)))
+        s = Server(ex, 64 << 30, keep_results=False)
+        run_trace_served(s, reqs, arrivals, timeout=60)
+        assert not s.failed, [r.error for r in s.failed]
+        assert len(s.completed) == len(reqs)
+        for r in reqs:
+            np.testing.assert_array_equal(ex.got[r.rid], expected(r), err_msg="trace %d request %d" % (trace, r.rid))
+        assert sum(len(v) for v in ex.buf_pool.values()) >= 1
