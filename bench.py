@@ -265,8 +265,17 @@ def bench_serving(M, dev, seconds):
                        "served": serve.latency_stats(srv.completed, 0.0),
                        "plain": serve.latency_stats(plain, 0.0),
                        "served_launches": srv.launches, "served_peak_hbm_gb": srv.peak_used / 2**30})
+    # device-only latency: the chain's launches on one resident page, no
+    # copies and no queueing, page by page (the plain path is warm by now)
+    runner.timing = True
+    for r in reqs(200):
+        runner.run_one(r)
+    runner.timing = False
+    dev_ms = np.array(runner.device_ms)
     return {"chain": "close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5", "budget_gb": 64,
             "seconds_per_trace": seconds,
+            "device_only_ms": {"n": int(len(dev_ms)), "p50": float(np.percentile(dev_ms, 50)),
+                               "p99": float(np.percentile(dev_ms, 99)), "max": float(dev_ms.max())},
             "saturation_pages_s": {"plain": p0, "served": p1, "served_burst": p1_burst},
             "load_points": points}
 

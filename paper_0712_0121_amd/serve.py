@@ -369,6 +369,10 @@ class PlainRunner:
         import paper_0712_0121_amd as M
         self.M, self.torch = M, torch
         self.device = torch.device(device)
+        # with timing set, run_one also records the device time of the
+        # chain's launches alone (no copies) into device_ms
+        self.timing = False
+        self.device_ms = []
 
     @staticmethod
     def elementary(chain):
@@ -390,12 +394,19 @@ class PlainRunner:
         a = M.Bitmap.empty(r.W, r.H, device=self.device)
         b = M.Bitmap.empty(r.W, r.H, device=self.device)
         a.words.copy_(host[:, : a.stride], non_blocking=True)
+        if self.timing:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
         for op, se in self.elementary(r.chain):
             M.PACKED[op](b, a, se)
             a, b = b, a
+        if self.timing:
+            e1.record()
         out = torch.empty((r.H, a.stride), dtype=torch.int64, pin_memory=True)
         out.copy_(a.words, non_blocking=True)
         torch.cuda.current_stream().synchronize()
+        if self.timing:
+            self.device_ms.append(e0.elapsed_time(e1))
         return out.numpy().view(np.uint64)
 
 

@@ -33,6 +33,11 @@ def make_requests(n, seed=5):
     return out
 
 
+def clone(reqs):
+    from paper_0712_0121_amd.serve import Request
+    return [Request(r.rid, r.W, r.H, r.words, r.chain) for r in reqs]
+
+
 def expected(r):
     img = oracle.unpack(r.words.numpy().view(np.uint64), r.W)
     for op, se in r.chain:
@@ -40,17 +45,18 @@ def expected(r):
     return oracle.pack(img)
 
 
-def served(reqs, arrivals, budget=64 << 30):
+def served(reqs, arrivals, budget=64 << 30, ex=None):
     from paper_0712_0121_amd.serve import GpuExecutor, Server, run_trace_served
-    s = Server(GpuExecutor(), budget_bytes=budget)
+    s = Server(GpuExecutor() if ex is None else ex, budget_bytes=budget)
     run_trace_served(s, reqs, arrivals, timeout=60)
     assert not s.failed, [r.error for r in s.failed]
     return s
 
 
 def test_mix_equals_alone_equals_plain_equals_oracle():
-    from paper_0712_0121_amd.serve import PlainRunner
-    reqs = make_requests(20)
+    from paper_0712_0121_amd.serve import GpuExecutor, PlainRunner
+    N = 100
+    reqs = make_requests(N)
     # staggered arrivals (some while others run), and every third request
     # arriving together with the one before it, so launches must be shared
     gaps = np.random.default_rng(1).exponential(0.0005, len(reqs))
@@ -60,11 +66,12 @@ def test_mix_equals_alone_equals_plain_equals_oracle():
     assert len(s.completed) == len(reqs)
     assert s.launches < 4 * len(reqs)           # operations shared launches
     mix = {r.rid: r.result.copy() for r in reqs}
-    for r in make_requests(20):
-        s1 = served([r], np.zeros(1))
+    alone_ex = GpuExecutor()
+    for r in clone(reqs):
+        s1 = served([r], np.zeros(1), ex=alone_ex)
         np.testing.assert_array_equal(r.result, mix[r.rid], err_msg="request %d alone vs mix" % r.rid)
     plain = PlainRunner()
-    for r in make_requests(20)[:6]:
+    for r in clone(reqs)[:6]:
         np.testing.assert_array_equal(plain.run_one(r), mix[r.rid])
     for r in reqs:
         np.testing.assert_array_equal(mix[r.rid], expected(r), err_msg="request %d vs oracle" % r.rid)
