@@ -431,6 +431,92 @@ def bench_masks(M, dev, src):
     return out
 
 
+def bench_density(M, dev, pages=64, distinct=4):
+    """Run-length density sweep: batches of 64 letter-size pages at 1 %, 10 %
+    and 40 % black (rectangles plus XOR noise, about 2, 20 and 60 runs per
+    row), erosion and dilation by 1x41 (horizontal) and 41x1 (vertical):
+    runs resident, bitmap -> runs -> operation -> bitmap end to end, and the
+    packed path on the same pages, plus the conversions alone.  %HBM is on
+    the algorithmic bytes: 8 B per run in and out and 4 B per row offset of
+    each for runs, one read and one write of the words for packed."""
+    import torch
+    import pagegen
+    W, H, P = LETTER_W, LETTER_H, pages
+    nw = (W + 63) // 64
+    ses = (("1x41", (41, 1, 20, 0)), ("41x1", (1, 41, 0, 20)))
+    out = {}
+    for d in (0.01, 0.10, 0.40):
+        pool = [pagegen.density_page(d, 4000 + i).words() for i in range(distinct)]
+        host = np.concatenate([pool[i % distinct] for i in range(P)])
+        src = M.Bitmap.from_words(host, W, npages=P, device=dev)
+        del host, pool
+        dst = M.Bitmap.empty(W, H, P, device=dev)
+        ws_c = torch.empty(max(M.morph_pack_to_rle_workspace_bytes(W, H * P), 1), dtype=torch.uint8, device=dev)
+        r_in = M.RLE.empty(W, H, P, device=dev)
+        r_out = M.RLE.empty(W, H, P, device=dev)
+        M.morph_pack_to_rle(r_in, src, ws_c)
+        n_in = int(r_in.row_ptr[-1].item())
+        px = W * H * P
+        img_b = 2.0 * nw * 8 * H * P
+        t_p2r = time_ms(lambda: M.morph_pack_to_rle(r_in, src, ws_c))
+        t_r2p = time_ms(lambda: M.morph_rle_to_pack(dst, r_in))
+        row = {"runs_per_row": n_in / (H * P), "black": float(d),
+               "pack_to_rle_ms": t_p2r, "rle_to_pack_ms": t_r2p, "ops": {}}
+        for name, se in ses:
+            for op in ("erode", "dilate"):
+                ws_r = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, P, se), 1), dtype=torch.uint8, device=dev)
+                wsp_n = M.morph_workspace_bytes(op, 0, W, H * P, se)
+                ws_p = torch.empty(wsp_n, dtype=torch.uint8, device=dev) if wsp_n else None
+                t_rle = time_ms(lambda: M.RLE_OPS[op](r_out, r_in, se, ws_r))
+                n_out = int(r_out.row_ptr[-1].item())
+                b_rle = 8.0 * (n_in + n_out) + 8.0 * (H * P + 1)
+
+                def e2e():
+                    M.morph_pack_to_rle(r_in, src, ws_c)
+                    M.RLE_OPS[op](r_out, r_in, se, ws_r)
+                    M.morph_rle_to_pack(dst, r_out)
+                t_e2e = time_ms(e2e)
+                t_pk = time_ms(lambda: M.PACKED[op](dst, src, se, ws_p))
+                row["ops"]["%s %s" % (op, name)] = {
+                    "rle_ms": t_rle, "rle_gpixel_s": px / (t_rle / 1e3) / 1e9,
+                    "rle_hbm_frac": b_rle / (t_rle / 1e3) / 1e9 / HBM_PEAK_GBS, "runs_out": n_out,
+                    "end_to_end_ms": t_e2e, "end_to_end_gpixel_s": px / (t_e2e / 1e3) / 1e9,
+                    "packed_ms": t_pk, "packed_gpixel_s": px / (t_pk / 1e3) / 1e9,
+                    "packed_hbm_frac": img_b / (t_pk / 1e3) / 1e9 / HBM_PEAK_GBS,
+                    "faster": "rle" if t_rle < t_pk else "packed"}
+                del ws_r, ws_p
+        out["%d%%" % round(100 * d)] = row
+        del src, dst, r_in, r_out, ws_c
+        torch.cuda.empty_cache()
+    return {"pages": P, "distinct": distinct, "densities": out}
+
+
+def bench_small(M, dev, reps=50):
+    """One 512x512 image (8 words per row; rectangles of 3-12 px along text
+    lines, 8 % black, salt noise): single-image latency of erosion and
+    dilation by 3x3, 9x1 (nine rows) and 1x9 on both paths, in microseconds
+    and Gpixel/s.  A page this small stays in cache: these are latencies."""
+    import torch
+    import pagegen
+    p = pagegen.small_page(1000)
+    src = M.Bitmap.from_words(p.words(), p.W, device=dev)
+    dst = M.Bitmap.empty(p.W, p.H, device=dev)
+    r_in = M.pack_to_rle(src)
+    r_out = M.RLE.empty(p.W, p.H, device=dev)
+    out = {}
+    for name, se in (("3x3", (3, 3, 1, 1)), ("9x1", (1, 9, 0, 4)), ("1x9", (9, 1, 4, 0))):
+        for op in ("erode", "dilate"):
+            wsp_n = M.morph_workspace_bytes(op, 0, p.W, p.H, se)
+            ws_p = torch.empty(wsp_n, dtype=torch.uint8, device=dev) if wsp_n else None
+            ws_r = torch.empty(max(M.morph_rle_workspace_bytes(op, p.W, p.H, 1, se), 1), dtype=torch.uint8, device=dev)
+            t_pk = time_ms(lambda: M.PACKED[op](dst, src, se, ws_p), reps)
+            t_rl = time_ms(lambda: M.RLE_OPS[op](r_out, r_in, se, ws_r), reps)
+            out["%s %s" % (op, name)] = {"packed_us": t_pk * 1e3, "rle_us": t_rl * 1e3,
+                                         "packed_gpixel_s": p.W * p.H / (t_pk / 1e3) / 1e9,
+                                         "rle_gpixel_s": p.W * p.H / (t_rl / 1e3) / 1e9}
+    return {"image": "512x512, %.1f%% black" % (100.0 * p.img.mean()), "ops": out}
+
+
 def bench_repr(M, dev, tuner):
     """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
     (conversions included), as the autotuner records it."""
@@ -652,6 +738,8 @@ def main():
         tuner = Tuner(device="cuda:0")
         out["batched"] = bench_batched(M, dev, tuner)
         out["repr_choice"] = bench_repr(M, dev, tuner)
+        out["density_sweep"] = bench_density(M, dev)
+        out["small_image"] = bench_small(M, dev)
         out["serving"] = bench_serving(M, dev, args.serve_seconds)
         out["transpose"] = bench_transpose(M, dev, src, breakdown.get("rle", {}).get("ms_per_op"))
         out["components"] = bench_components(M, dev, src)
