@@ -429,6 +429,69 @@ __device__ __forceinline__ int group_last(int x)
     return __builtin_amdgcn_update_dpp(0, x, 0x15f, 0xf, 0xf, false);
 }
 
+// ------------------------------------------- packed -> runs, narrow rows
+// The same transitions with one 16-lane group per row (four rows a wave):
+// lane k takes words k, k + 16, ...; the bit before a word comes from the
+// lane before (DPP row_shr) or, for lane 0, from lane 15 of the block
+// before.  A row of 40 words is three blocks instead of a wave with 24 idle
+// lanes, and a quarter of the waves.  Used for rows of up to 128 words.
+constexpr int kNarrowRowWords = 128;
+
+template <bool EMIT>
+__global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
+    const uint64_t *__restrict__ words, int nw, int stride, int H, int R, long long page_words,
+    uint64_t padmask, int *__restrict__ counts, const int *__restrict__ row_ptr,
+    int *__restrict__ runs, long long cap, unsigned long long *trace)
+{
+    const int r = (int)(blockIdx.x * (unsigned)kGroupsPerBlock + (threadIdx.x >> 4));
+    if (r >= R) return;                    // whole group
+    const int gl = glane();
+    const int page = r / H, y = r - page * H;
+    const uint64_t *row = words + (long long)page * page_words + (long long)y * stride;
+    const long long obase = EMIT ? row_ptr[r] : 0;
+    int cstart = 0, cend = 0;
+    int prev = 0;                          // bit 63 of the word before this block
+    for (int j0 = 0; j0 <= nw; j0 += kGroup) {
+        const int j = j0 + gl;
+        uint64_t a = 0;
+        if (j < nw) {
+            a = row[j];
+            if (j == nw - 1) a &= padmask;
+        }
+        const int top = (int)(a >> 63);
+        const int up = __builtin_amdgcn_update_dpp(prev, top, 0x111, 0xf, 0xf, false);   // row_shr:1
+        const uint64_t sh = (a << 1) | (uint64_t)(unsigned)up;
+        uint64_t st = a & ~sh, en = ~a & sh;
+        if (j > nw) {
+            st = 0;
+            en = 0;
+        }
+        const int ns = __popcll(st), ne = __popcll(en);
+        const int is = group_incl_scan(ns), ie = group_incl_scan(ne);
+        if (EMIT) {
+            long long k = obase + cstart + is - ns;
+            while (st) {
+                const int b = __ffsll((unsigned long long)st) - 1;
+                if (k < cap) runs[2 * k] = 64 * j + b;
+                k++;
+                st &= st - 1;
+            }
+            k = obase + cend + ie - ne;
+            while (en) {
+                const int b = __ffsll((unsigned long long)en) - 1;
+                if (k < cap) runs[2 * k + 1] = 64 * j + b;
+                k++;
+                en &= en - 1;
+            }
+        }
+        cstart += group_last(is);
+        cend += group_last(ie);
+        prev = group_last(top);
+    }
+    if (!EMIT && gl == 0) counts[r] = cstart;
+    if (EMIT && trace && gl == 0) trace_add(trace, 0, (unsigned long long)cstart);
+}
+
 // ------------------------------------------------------ within-line pass
 // Erosion of every row by a 1 x w element with origin cx (section "Within-
 // Line Morphological Operations"): run [s, e) becomes [s + cx, e - (w-1-cx)),
@@ -1288,13 +1351,24 @@ hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, vo
     const unsigned g = blocks_for(R, kRowWaves);
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_PACK_TO_RLE, s);
-    hipLaunchKernelGGL((pack_to_rle_kernel<false>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
-                       src.stride_words, src.height, R, pw, pad, counts, nullptr, nullptr, 0LL, nullptr);
+    const bool narrow = nw <= kNarrowRowWords;
+    const unsigned gg = blocks_for(R, kGroupsPerBlock);
+    if (narrow)
+        hipLaunchKernelGGL((pack_to_rle_group_kernel<false>), dim3(gg), dim3(256), 0, s, src.words, nw,
+                           src.stride_words, src.height, R, pw, pad, counts, nullptr, nullptr, 0LL, nullptr);
+    else
+        hipLaunchKernelGGL((pack_to_rle_kernel<false>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
+                           src.stride_words, src.height, R, pw, pad, counts, nullptr, nullptr, 0LL, nullptr);
     hipError_t e = exclusive_scan(counts, R, dst.row_ptr, tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((pack_to_rle_kernel<true>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
-                       src.stride_words, src.height, R, pw, pad, nullptr, dst.row_ptr, dst.runs,
-                       (long long)dst.capacity, trace_block(tr, MORPH_K_PACK_TO_RLE));
+    if (narrow)
+        hipLaunchKernelGGL((pack_to_rle_group_kernel<true>), dim3(gg), dim3(256), 0, s, src.words, nw,
+                           src.stride_words, src.height, R, pw, pad, nullptr, dst.row_ptr, dst.runs,
+                           (long long)dst.capacity, trace_block(tr, MORPH_K_PACK_TO_RLE));
+    else
+        hipLaunchKernelGGL((pack_to_rle_kernel<true>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
+                           src.stride_words, src.height, R, pw, pad, nullptr, dst.row_ptr, dst.runs,
+                           (long long)dst.capacity, trace_block(tr, MORPH_K_PACK_TO_RLE));
     trace_after(MORPH_K_PACK_TO_RLE, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
