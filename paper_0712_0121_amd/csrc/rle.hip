@@ -890,6 +890,51 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     }
 }
 
+// ------------------------------------------- runs -> packed, narrow rows
+// One 16-lane group per row of up to 128 words (four rows a wave): the row
+// is cleared in this group's LDS buffer, each lane ORs its runs in (the
+// words a run covers whole are stored, the partial words at its ends ORed:
+// runs are disjoint, so only those can be shared), and the row goes out in
+// 128-byte stores.  Run bounds are clamped to the row and offsets to the
+// run capacity, so damaged input cannot reach outside either buffer.
+__global__ __launch_bounds__(256) void rle_to_pack_group_kernel(const int *__restrict__ row_ptr,
+                                                                const int *__restrict__ runs, int nw,
+                                                                int R, int H, uint64_t *__restrict__ words,
+                                                                int stride, long long page_words, long long cap,
+                                                                unsigned long long *trace)
+{
+    __shared__ uint64_t rowbuf[kGroupsPerBlock][kNarrowRowWords];
+    const int r = (int)(blockIdx.x * (unsigned)kGroupsPerBlock + (threadIdx.x >> 4));
+    if (r >= R) return;                    // whole group; only wave-level syncs below
+    const int gl = glane();
+    uint64_t *buf = rowbuf[threadIdx.x >> 4];
+    for (int j = gl; j < nw; j += kGroup) buf[j] = 0;
+    wave_lds_sync();
+    const long long b0 = min((long long)max(row_ptr[r], 0), cap);
+    const long long b1 = max(b0, min((long long)row_ptr[r + 1], cap));
+    const int xmax = 64 * nw;
+    for (long long k = b0 + gl; k < b1; k += kGroup) {
+        const int2 v = reinterpret_cast<const int2 *>(runs)[k];
+        const int s0 = max(v.x, 0), e0 = min(v.y, xmax);
+        if (s0 >= e0) continue;
+        const int ws = s0 >> 6, we = (e0 - 1) >> 6;
+        const uint64_t lo = ~0ull << (s0 & 63);
+        const uint64_t hi = ~0ull >> (63 - ((e0 - 1) & 63));
+        if (ws == we) {
+            atomicOr((unsigned long long *)&buf[ws], (unsigned long long)(lo & hi));
+        } else {
+            atomicOr((unsigned long long *)&buf[ws], (unsigned long long)lo);
+            for (int w = ws + 1; w < we; w++) buf[w] = ~0ull;
+            atomicOr((unsigned long long *)&buf[we], (unsigned long long)hi);
+        }
+    }
+    wave_lds_sync();
+    const int page = r / H, y = r - page * H;
+    uint64_t *out = words + (long long)page * page_words + (long long)y * stride;
+    for (int j = gl; j < nw; j += kGroup) out[j] = buf[j];
+    if (trace && gl == 0) trace_add(trace, (unsigned long long)(b1 - b0), 0);
+}
+
 // ----------------------------------------------------- block prefix scans
 // Between-line erosion by h rows in two launches for tall elements: the
 // extended rows 0 .. NA-1 of a page (row x = stored row x - off, a full
@@ -1380,10 +1425,16 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_RLE_TO_PACK, s);
     if ((long long)R * nw >= 0xffffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for((long long)R * nw, 256)), dim3(256), 0, s,
-                       src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
-                       (long long)dst.stride_words * dst.height, (long long)src.capacity,
-                       trace_block(tr, MORPH_K_RLE_TO_PACK));
+    if (nw <= kNarrowRowWords)
+        hipLaunchKernelGGL(rle_to_pack_group_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s,
+                           src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
+                           (long long)dst.stride_words * dst.height, (long long)src.capacity,
+                           trace_block(tr, MORPH_K_RLE_TO_PACK));
+    else
+        hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for((long long)R * nw, 256)), dim3(256), 0, s,
+                           src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
+                           (long long)dst.stride_words * dst.height, (long long)src.capacity,
+                           trace_block(tr, MORPH_K_RLE_TO_PACK));
     trace_after(MORPH_K_RLE_TO_PACK, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
