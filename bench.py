@@ -151,9 +151,13 @@ def bench_batched(M, dev, tuner, n=256):
     px = sum(it.page.W * it.page.H for it in items)
     alg = sum(2 * 8 * ((it.page.W + 63) // 64) * it.page.H for it in items)
 
+    import torch
+    ws_n = max([1] + [M.morph_workspace_bytes(it.op, 0, it.page.W, it.page.H, it.se) for it in items])
+    ws_pp = torch.empty(ws_n, dtype=torch.uint8, device=dev)      # one page's split operations at a time
+
     def per_page():
         for it, s_, d_ in zip(items, srcs, dsts):
-            M.PACKED[it.op](d_, s_, it.se)
+            M.PACKED[it.op](d_, s_, it.se, ws_pp)
     t_pp = time_ms(per_page, 3)
     plan = M.BatchPlan([(d_, s_, it.op, it.se) for it, s_, d_ in zip(items, srcs, dsts)])
     t_b = time_ms(lambda: plan.run(use_graph=True))
@@ -710,12 +714,14 @@ def main():
         w1 = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, 1, se) for op in OPS for _, se in LETTER_SES),
                          dtype=torch.uint8, device=dev)
         w2 = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
+        w0 = torch.empty(max([1] + [M.morph_workspace_bytes(op, 0, W, H, se) for op, _, se in packed_jobs]),
+                         dtype=torch.uint8, device=dev)
         lat_pk, lat_all = [], []
         for rep in range(args.latency_reps + 3):
             torch.cuda.synchronize()
             t = time.perf_counter()
             for op, _, se in packed_jobs:
-                M.PACKED[op](od, one, se)
+                M.PACKED[op](od, one, se, w0)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             M.morph_pack_to_rle(r1, one, w2)

@@ -398,7 +398,9 @@ class PlainRunner:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
         for op, se in self.elementary(r.chain):
-            M.PACKED[op](b, a, se)
+            n = M.morph_workspace_bytes(op, 0, r.W, r.H, se)     # 0 unless the element is split
+            ws = torch.empty(n, dtype=torch.uint8, device=self.device) if n else None
+            M.PACKED[op](b, a, se, ws)
             a, b = b, a
         if self.timing:
             e1.record()

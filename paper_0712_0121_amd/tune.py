@@ -168,7 +168,9 @@ class Tuner:
             for op in ops:
                 for se in ses:
                     w_rle = torch.empty(M.morph_rle_workspace_bytes(op, W, H, 1, se), dtype=torch.uint8, device=dev)
-                    t_pk = self._time(lambda: M.PACKED[op](dst, src, se))
+                    n_pk = M.morph_workspace_bytes(op, 0, W, H, se)
+                    w_pk = torch.empty(n_pk, dtype=torch.uint8, device=dev) if n_pk else None
+                    t_pk = self._time(lambda: M.PACKED[op](dst, src, se, w_pk))
 
                     def rle_path():
                         M.morph_pack_to_rle(r_in, src, w_p2r)
