@@ -744,12 +744,13 @@ __device__ __forceinline__ int group_intersect_staged(const int2 (&a)[kARegs], i
 // Candidates of a row held in registers (lane k holds raw runs k + 16 m):
 // in place, the gaps of the complement taking the end of the run before
 // from the lane before (or lane 15 of the block before).
-__device__ __forceinline__ void shrink_regs(const RowX &x, int2 (&v)[kARegs], int n)
+__device__ __forceinline__ void shrink_regs(const RowX &x, int2 (&v)[kARegs], int n, int nblk)
 {
     const int gl = glane();
     int prev_end = 0;
 #pragma unroll
     for (int m = 0; m < kARegs; m++) {
+        if (m >= nblk) break;                  // wave-uniform
         const int k = m * kGroup + gl;
         if (x.comp) {
             const int pe = __builtin_amdgcn_update_dpp(prev_end, v[m].y, 0x111, 0xf, 0xf, false);
@@ -857,22 +858,32 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     if (cs == 0) {
         cnt = 0;
     } else if (cl <= kStageRuns) {
+        // the blocks of 16 candidates that any row pair of this wave needs,
+        // as a scalar, read from one lane of each group: the block loops
+        // below end on a uniform branch.  A group outside this branch leaves
+        // a stale value in its lanes, which can only raise the bound.
+        const int nm = max(max(__builtin_amdgcn_readlane(cl, 0), __builtin_amdgcn_readlane(cl, 16)),
+                           max(__builtin_amdgcn_readlane(cl, 32), __builtin_amdgcn_readlane(cl, 48)));
+        const int nblk = (nm + kGroup - 1) / kGroup;
         const int2 *S2 = (const int2 *)S, *L2 = (const int2 *)L;
         int2 a[kARegs], b[kARegs];
 #pragma unroll
         for (int m = 0; m < kARegs; m++) {
+            if (m >= nblk) break;
             const int k = m * kGroup + gl;
             a[m] = k < ns ? S2[k] : make_int2(0, 0);
             b[m] = k < nl ? L2[k] : make_int2(0, 0);
         }
         if (ROWX) {
-            shrink_regs(x, a, ns);
-            shrink_regs(x, b, nl);
+            shrink_regs(x, a, ns, nblk);
+            shrink_regs(x, b, nl, nblk);
         }
         int2 *sB = stage[threadIdx.x >> 4];
 #pragma unroll
-        for (int m = 0; m < kARegs; m++)
+        for (int m = 0; m < kARegs; m++) {
+            if (m >= nblk) break;
             if (m * kGroup + gl < cl) sB[m * kGroup + gl] = b[m];
+        }
         wave_lds_sync();
         cnt = group_intersect_staged<ROWX>(a, cs, sB, cl, (int2 *)o, (int)cap_row);
     } else {
