@@ -492,6 +492,17 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
     if (EMIT && trace && gl == 0) trace_add(trace, 0, (unsigned long long)cstart);
 }
 
+// The number of 16-run blocks the longest of the wave's four rows needs
+// (n runs each), read from one lane of each group: loops over register
+// blocks end on a uniform branch.  Groups that left early leave stale
+// values in their lanes, which can only raise the bound.
+__device__ __forceinline__ int wave_blocks(int n)
+{
+    const int m = max(max(__builtin_amdgcn_readlane(n, 0), __builtin_amdgcn_readlane(n, 16)),
+                      max(__builtin_amdgcn_readlane(n, 32), __builtin_amdgcn_readlane(n, 48)));
+    return (m + kGroup - 1) / kGroup;
+}
+
 // ------------------------------------------------------ within-line pass
 // Erosion of every row by a 1 x w element with origin cx (section "Within-
 // Line Morphological Operations"): run [s, e) becomes [s + cx, e - (w-1-cx)),
@@ -529,9 +540,11 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
         // the whole row in registers (lane k holds runs k + 16 m), every load
         // issued before the first use
         const int2 *r2 = (const int2 *)rr;
+        const int nblk = wave_blocks(ncand);
         int2 v[kARegs];
 #pragma unroll
         for (int m = 0; m < kARegs; m++) {
+            if (m >= nblk) break;
             const int k = m * kGroup + gl;
             v[m] = k < n ? r2[k] : make_int2(0, 0);
         }
@@ -858,13 +871,8 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     if (cs == 0) {
         cnt = 0;
     } else if (cl <= kStageRuns) {
-        // the blocks of 16 candidates that any row pair of this wave needs,
-        // as a scalar, read from one lane of each group: the block loops
-        // below end on a uniform branch.  A group outside this branch leaves
-        // a stale value in its lanes, which can only raise the bound.
-        const int nm = max(max(__builtin_amdgcn_readlane(cl, 0), __builtin_amdgcn_readlane(cl, 16)),
-                           max(__builtin_amdgcn_readlane(cl, 32), __builtin_amdgcn_readlane(cl, 48)));
-        const int nblk = (nm + kGroup - 1) / kGroup;
+        // the blocks of 16 candidates that any row pair of this wave needs
+        const int nblk = wave_blocks(cl);
         const int2 *S2 = (const int2 *)S, *L2 = (const int2 *)L;
         int2 a[kARegs], b[kARegs];
 #pragma unroll
@@ -1115,9 +1123,11 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(RowsIn in, int R, int W,
     if ((comp ? n + 1 : n) <= kStageRuns) {
         // the whole row in registers (lane k holds runs k + 16 m)
         const int2 *r2 = (const int2 *)rr;
+        const int nblk = wave_blocks(comp ? n + 1 : n);
         int2 v[kARegs];
 #pragma unroll
         for (int m = 0; m < kARegs; m++) {
+            if (m >= nblk) break;
             const int k = m * kGroup + gl;
             v[m] = k < n ? r2[k] : make_int2(0, 0);
         }
