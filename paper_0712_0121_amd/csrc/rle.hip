@@ -109,6 +109,37 @@ __global__ __launch_bounds__(kScanThreads) void scan_mid_kernel(int *bsum, int n
     }
 }
 
+// The whole scan in one workgroup for short inputs (a page's rows): blocks
+// of kScanBlock in turn with a carry, the grand total at out[n].  One launch
+// instead of three, which is most of the scan's time on a single page.
+constexpr int kScanSingleMax = 4 * kScanBlock;
+
+__global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const int *__restrict__ in, int n,
+                                                                   int *__restrict__ out)
+{
+    __shared__ int smem[kScanThreads / 64];
+    int carry = 0;
+    for (int b0 = 0; b0 < n; b0 += kScanBlock) {
+        const int base = b0 + (int)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int s = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            v[i] = (base + i < n) ? in[base + i] : 0;
+            s += v[i];
+        }
+        int tot;
+        int run = block_excl_scan(s, smem, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            if (base + i < n) out[base + i] = run;
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const int *__restrict__ in, int n,
                                                                  const int *__restrict__ bsum,
                                                                  int *__restrict__ out)
@@ -1389,6 +1420,10 @@ hipError_t exclusive_scan(const int *in, int n, int *out, int *tmp, hipStream_t 
 {
     if (n == 0) {
         hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, s, out);
+        return hipGetLastError();
+    }
+    if (n <= kScanSingleMax) {
+        hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, s, in, n, out);
         return hipGetLastError();
     }
     const unsigned nb = blocks_for(n, kScanBlock);
