@@ -247,13 +247,19 @@ def bench_serving(M, dev, seconds):
             serve.run_trace_served(srv, burst, np.zeros(len(burst)))
             p1_burst = len(burst) / (time.perf_counter() - t)
     # sustained served capacity: a Poisson stream above it for 2 s, counting
-    # completions per second (a burst forms larger batches than arrivals do)
-    arrivals = pagegen.poisson_trace(1.5 * p1_burst, 2.0, seed=5002)
-    sustained = reqs(len(arrivals))
-    with _frozen_requests():
-        srv = serve.Server(ex, budget, keep_results=False)
-        serve.run_trace_served(srv, sustained, arrivals, timeout=120)
-    p1 = serve.latency_stats(srv.completed, 0.0)["pages_per_s"]
+    # completions per second (a burst forms larger batches than arrivals do).
+    # Measured twice and the lower kept: the served path is host-bound near
+    # its capacity, and a high estimate puts the 0.9x point past it
+    p1_runs = []
+    for rep in range(2):
+        arrivals = pagegen.poisson_trace(1.5 * p1_burst, 2.0, seed=5002 + rep)
+        sustained = reqs(len(arrivals))
+        with _frozen_requests():
+            srv = serve.Server(ex, budget, keep_results=False)
+            serve.run_trace_served(srv, sustained, arrivals, timeout=120)
+        p1_runs.append(serve.latency_stats(srv.completed, 0.0)["pages_per_s"])
+        del sustained, srv
+    p1 = min(p1_runs)
     points = []
     for name, qps in (("0.5x plain saturation", 0.5 * p0), ("0.9x plain saturation", 0.9 * p0),
                       ("0.9x served saturation", 0.9 * p1)):
@@ -280,7 +286,7 @@ def bench_serving(M, dev, seconds):
             "seconds_per_trace": seconds,
             "device_only_ms": {"n": int(len(dev_ms)), "p50": float(np.percentile(dev_ms, 50)),
                                "p99": float(np.percentile(dev_ms, 99)), "max": float(dev_ms.max())},
-            "saturation_pages_s": {"plain": p0, "served": p1, "served_burst": p1_burst},
+            "saturation_pages_s": {"plain": p0, "served": p1, "served_runs": p1_runs, "served_burst": p1_burst},
             "load_points": points}
 
 
