@@ -39,8 +39,10 @@ def assert_rle_equal(got: "M.RLE", img, what=""):
 
 
 # --------------------------------------------------------------- conversion
-@pytest.mark.parametrize("W", [1, 5, 63, 64, 65, 128, 129, 2550, 4096, 4097, 5100])
+@pytest.mark.parametrize("W", [1, 5, 63, 64, 65, 128, 129, 2550, 4096, 4097, 5100, 8192, 8193, 10000])
 def test_pack_to_rle_matches_oracle(W):
+    """Rows of up to 128 words take one 16-lane group each, wider rows a
+    wave each: widths on both sides of 8192 pixels."""
     H = 23
     for p in (0.0, 0.02, 0.5, 0.97, 1.0):
         img = rnd_img(int(W * 10 + p * 100), H, W, p)
@@ -66,7 +68,7 @@ def test_pack_to_rle_capacity_overflow_reports_total():
     np.testing.assert_array_equal(r.runs[:cap].cpu().numpy(), wruns[:cap])
 
 
-@pytest.mark.parametrize("W", [1, 64, 65, 700, 2550, 5100])
+@pytest.mark.parametrize("W", [1, 64, 65, 700, 2550, 5100, 8192, 8193, 10000])
 def test_rle_to_pack_round_trip(W):
     img = blobs_img(W, 31, W, 0.4)
     r = to_rle_gpu(img)
