@@ -50,6 +50,15 @@ def test_pack_to_rle_matches_oracle(W):
         assert_rle_equal(to_rle_gpu(img, stride=stride, seed=W), img, "W=%d p=%g" % (W, p))
 
 
+@pytest.mark.parametrize("H", [2047, 2048, 2049, 8191, 8192, 8193])
+def test_row_offsets_around_scan_limits(H):
+    """row_ptr is the prefix sum of the row counts: up to 8192 rows it is
+    computed by one workgroup in blocks of 2048, beyond that by three
+    launches; row counts on both sides of both limits."""
+    img = rnd_img(H, H, 70, 0.3)
+    assert_rle_equal(to_rle_gpu(img), img, "H=%d" % H)
+
+
 def test_alternating_pixels_worst_case():
     W, H = 2550, 9
     img = np.tile((np.arange(W) % 2 == 0).astype(np.uint8), (H, 1))
