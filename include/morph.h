@@ -125,7 +125,13 @@ const char *morph_last_hip_error(void);
  * (dilation)).  dst and src must have equal width, height and npages;
  * strides may differ.  ws/ws_bytes: device workspace of at least
  * morph_workspace_bytes(op, MORPH_PACKED, ...) bytes (0 for most elements;
- * ws may then be NULL).
+ * ws may then be NULL).  One image of workspace is needed when the
+ * operation runs as two launches: an element reaching more than 64 pixels
+ * sideways or 128 rows down (split by the composition law), or an opening
+ * or closing whose two stages bring more halo rows than a fused tile holds
+ * output rows (51 x 51 on 2550-pixel rows, for instance).  Whether that
+ * happens depends on the element and the width only, so the size queried
+ * for a stack's total rows covers every page height.
  */
 int morph_erode_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
                             void *ws, size_t ws_bytes, morph_stream_t stream);
