@@ -631,12 +631,14 @@ static bool transposed_shape(int dw, int dh, int dp, int sw, int sh, int sp)
     return dw == sh && dh == sw && dp == sp;
 }
 
-// Workspace of a run-length transpose: the transposed bitmap, then the
-// scratch of the re-encoding.
+// Workspace of a run-length transpose: the transposed bitmap, the scratch
+// of the re-encoding, then the source decoded in its own orientation (rows
+// of up to 128 words are decoded there and transposed as a bitmap).
 static size_t transpose_rle_ws(int W, int H, int P)
 {
     const size_t rows = (size_t)W * P;
-    return round256(image_bytes(H, (int)rows)) + round256(morph_pack_to_rle_workspace_bytes(H, (int)rows));
+    return round256(image_bytes(H, (int)rows)) + round256(morph_pack_to_rle_workspace_bytes(H, (int)rows)) +
+           round256(image_bytes(W, H * P));
 }
 
 // Workspace of the transpose-based rectangle operation: one bitmap buffer
@@ -646,7 +648,7 @@ static size_t transpose_rle_ws(int W, int H, int P)
 // re-encoding scratch and, for opening and closing, that last pass's
 // workspace.
 struct RletWs {
-    size_t bm, rp, runs, p2r, rowop, total;
+    size_t bm, rp, runs, p2r, rowop, tmp, total;
     long long cap;
 };
 
@@ -665,7 +667,9 @@ static RletWs rlet_ws(int op, int W, int H, int P, morph_se_t se)
         w.rowop = round256(morph_workspace_bytes(op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE, MORPH_PACKED,
                                                  W, (int)rows, row));
     }
-    w.total = w.bm + w.rp + w.runs + w.p2r + w.rowop;
+    // each decode's source in its own orientation, before the transpose
+    w.tmp = round256(std::max(image_bytes(W, (int)rows), image_bytes(H, (int)rowsT)));
+    w.total = w.bm + w.rp + w.runs + w.p2r + w.rowop + w.tmp;
     return w;
 }
 
@@ -694,9 +698,10 @@ static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morp
     case MORPH_OPEN: col = LineOp{kLineOpen, se.h, se.cy, 0}; break;
     default: col = LineOp{kLineOpen, se.h, se.h - 1 - se.cy, 1}; break;   // closing: the gaps' opening
     }
-    hipError_t e = rle_decode_transposed(T1, src, row, s);
+    uint64_t *tmp = (uint64_t *)(ws + L.bm + L.rp + L.runs + L.p2r + L.rowop);
+    hipError_t e = rle_decode_transposed(T1, src, row, s, tmp);
     if (e == hipSuccess) e = rle_from_packed(R1, T1, p2r, s);
-    if (e == hipSuccess) e = rle_decode_transposed(T2, R1, col, s);
+    if (e == hipSuccess) e = rle_decode_transposed(T2, R1, col, s, tmp);
     if (e == hipSuccess && (op == MORPH_ERODE || op == MORPH_DILATE)) e = rle_from_packed(dst, T2, p2r, s);
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
     if (op == MORPH_ERODE || op == MORPH_DILATE) return MORPH_OK;
@@ -743,7 +748,9 @@ int morph_transpose_rle(const morph_rle_t *dst, const morph_rle_t *src, void *ws
     const int W = src->width, H = src->height, P = src->npages;
     char *w = (char *)ws;
     const morph_bitmap_t T{(uint64_t *)w, H, W, (H + 63) / 64, P};
-    hipError_t e = rle_decode_transposed(T, *src, LineOp{kLineNone, 1, 0, 0}, (hipStream_t)stream);
+    uint64_t *tmp = (uint64_t *)(w + round256(image_bytes(H, W * P)) +
+                                 round256(morph_pack_to_rle_workspace_bytes(H, W * P)));
+    hipError_t e = rle_decode_transposed(T, *src, LineOp{kLineNone, 1, 0, 0}, (hipStream_t)stream, tmp);
     if (e == hipSuccess)
         e = rle_from_packed(*dst, T, w + round256(image_bytes(H, W * P)), (hipStream_t)stream);
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }

@@ -191,8 +191,10 @@ struct LineOp {
 };
 // Runs -> transposed packed bitmap (dst: width = src height, height = src
 // width), with op applied along the source rows.
+// tmp: a bitmap of src's own size (stride ceil(width/64)), used for rows of
+// up to 128 words (decode, then transpose); nullptr keeps the direct decode.
 hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op,
-                                 hipStream_t stream);
+                                 hipStream_t stream, uint64_t *tmp = nullptr);
 int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
 
 void set_hip_error(hipError_t e);

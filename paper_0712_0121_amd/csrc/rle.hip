@@ -942,16 +942,21 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
 
 // ------------------------------------------- runs -> packed, narrow rows
 // One 16-lane group per row of up to 128 words (four rows a wave): the row
-// is cleared in this group's LDS buffer, each lane ORs its runs in (the
-// words a run covers whole are stored, the partial words at its ends ORed:
-// runs are disjoint, so only those can be shared), and the row goes out in
-// 128-byte stores.  Run bounds are clamped to the row and offsets to the
-// run capacity, so damaged input cannot reach outside either buffer.
+// is cleared in this group's LDS buffer, each lane ORs its intervals in
+// (the words an interval covers whole are stored, the partial words at its
+// ends ORed), and the row goes out in 128-byte pieces.  With a within-line
+// operation (op.mode != kLineNone) each run, or with op.comp each gap
+// between runs (including the two at the borders), is first eroded,
+// dilated or opened along the row, and with op.comp the row is then
+// complemented.  Dilated intervals may overlap; every write is an OR or a
+// store of all ones, so the order does not matter.  Interval bounds are
+// clamped to the row and offsets to the run capacity, so damaged input
+// cannot reach outside either buffer.
 __global__ __launch_bounds__(256) void rle_to_pack_group_kernel(const int *__restrict__ row_ptr,
                                                                 const int *__restrict__ runs, int nw,
-                                                                int R, int H, uint64_t *__restrict__ words,
+                                                                int R, int H, int W, uint64_t *__restrict__ words,
                                                                 int stride, long long page_words, long long cap,
-                                                                unsigned long long *trace)
+                                                                LineOp op, unsigned long long *trace)
 {
     __shared__ uint64_t rowbuf[kGroupsPerBlock][kNarrowRowWords];
     const int r = (int)(blockIdx.x * (unsigned)kGroupsPerBlock + (threadIdx.x >> 4));
@@ -962,10 +967,23 @@ __global__ __launch_bounds__(256) void rle_to_pack_group_kernel(const int *__res
     wave_lds_sync();
     const long long b0 = min((long long)max(row_ptr[r], 0), cap);
     const long long b1 = max(b0, min((long long)row_ptr[r + 1], cap));
+    const int n = (int)(b1 - b0);
+    const int2 *rr = reinterpret_cast<const int2 *>(runs) + b0;
     const int xmax = 64 * nw;
-    for (long long k = b0 + gl; k < b1; k += kGroup) {
-        const int2 v = reinterpret_cast<const int2 *>(runs)[k];
-        const int s0 = max(v.x, 0), e0 = min(v.y, xmax);
+    const int ni = op.comp ? n + 1 : n;
+    for (int k = gl; k < ni; k += kGroup) {
+        int s0, e0;
+        if (op.comp) {
+            s0 = (k == 0) ? 0 : rr[k - 1].y;
+            e0 = (k == n) ? W : rr[k].x;
+        } else {
+            const int2 v = rr[k];
+            s0 = v.x;
+            e0 = v.y;
+        }
+        if (op.mode != kLineNone && !line_interval(op, W, s0, e0)) continue;
+        s0 = max(s0, 0);
+        e0 = min(e0, xmax);
         if (s0 >= e0) continue;
         const int ws = s0 >> 6, we = (e0 - 1) >> 6;
         const uint64_t lo = ~0ull << (s0 & 63);
@@ -981,8 +999,15 @@ __global__ __launch_bounds__(256) void rle_to_pack_group_kernel(const int *__res
     wave_lds_sync();
     const int page = r / H, y = r - page * H;
     uint64_t *out = words + (long long)page * page_words + (long long)y * stride;
-    for (int j = gl; j < nw; j += kGroup) out[j] = buf[j];
-    if (trace && gl == 0) trace_add(trace, (unsigned long long)(b1 - b0), 0);
+    for (int j = gl; j < nw; j += kGroup) {
+        uint64_t v = buf[j];
+        if (op.comp) {
+            const int nb = min(64, W - 64 * j);
+            v = ~v & ((nb >= 64) ? ~0ull : ((1ull << nb) - 1));
+        }
+        out[j] = v;
+    }
+    if (trace && gl == 0) trace_add(trace, (unsigned long long)n, 0);
 }
 
 // ----------------------------------------------------- block prefix scans
@@ -1483,9 +1508,9 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
     if ((long long)R * nw >= 0xffffffffLL) return hipErrorInvalidValue;
     if (nw <= kNarrowRowWords)
         hipLaunchKernelGGL(rle_to_pack_group_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s,
-                           src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
+                           src.row_ptr, src.runs, nw, R, src.height, src.width, dst.words, dst.stride_words,
                            (long long)dst.stride_words * dst.height, (long long)src.capacity,
-                           trace_block(tr, MORPH_K_RLE_TO_PACK));
+                           LineOp{kLineNone, 1, 0, 0}, trace_block(tr, MORPH_K_RLE_TO_PACK));
     else
         hipLaunchKernelGGL(rle_to_pack_kernel, dim3(blocks_for((long long)R * nw, 256)), dim3(256), 0, s,
                            src.row_ptr, src.runs, nw, R, src.height, dst.words, dst.stride_words,
@@ -1496,10 +1521,28 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
 }
 
 hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op,
-                                 hipStream_t s)
+                                 hipStream_t s, uint64_t *tmp)
 {
     const int W = src.width, H = src.height;
     const int nw = (W + 63) / 64, nk = (H + 63) / 64;
+    if (tmp && nw <= kNarrowRowWords) {
+        // rows of up to 128 words: decoded with the operation into tmp in
+        // their own orientation, one group per row, then turned by the
+        // 64 x 64 bit-block transpose; both passes run near the memory's
+        // pace, where decoding straight into the transposed image streams
+        // each row's runs through one lane
+        const int R = H * src.npages;
+        const morph_bitmap_t T{tmp, W, H, nw, src.npages};
+        unsigned long long *tr = trace_counters();
+        trace_before(MORPH_K_DECODE_T, s);
+        hipLaunchKernelGGL(rle_to_pack_group_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s,
+                           src.row_ptr, src.runs, nw, R, H, W, tmp, nw, (long long)nw * H,
+                           (long long)src.capacity, op, trace_block(tr, MORPH_K_DECODE_T));
+        trace_after(MORPH_K_DECODE_T, s, 8.0 * (double)nw * R + 4.0 * ((double)R + 1));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return packed_transpose(dst, T, s);
+    }
     const int nstrips = (nw + kDecodeStrip - 1) / kDecodeStrip;
     const int kgroups = (nk + kDecodeWaves - 1) / kDecodeWaves;
     const long long total = (long long)nstrips * kgroups * src.npages;
