@@ -192,8 +192,9 @@ int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_s
 int morph_transpose_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_stream_t stream);
 /*
  * Run-length transpose: dst row x holds the runs of column x of src (the
- * runs are decoded 64 x 64 pixels at a time straight into the transposed
- * bitmap, which is then re-encoded).  dst->capacity must be at least
+ * runs are decoded into a bitmap, rows of up to 128 words in their own
+ * orientation and then transposed 64 x 64 pixels at a time, wider rows
+ * straight into the transposed bitmap, which is then re-encoded).  dst->capacity must be at least
  * morph_rle_max_runs(src->height, src->width * npages) (MORPH_E_CAPACITY);
  * ws: 256-byte aligned, at least morph_transpose_rle_workspace_bytes(src
  * width, src height, npages) bytes.
