@@ -115,6 +115,13 @@ const char *morph_version(void);
 const char *morph_strerror(int code);
 /* Message of the calling thread's last HIP failure ("" if none). */
 const char *morph_last_hip_error(void);
+/* Copies bytes from src to dst on stream, asynchronously (device memory or
+ * pinned host memory on either side), for callers that keep their page
+ * buffers in pools, such as a serving loop, and so need none of a framework
+ * copy's bookkeeping.  The buffers must stay allocated until the stream has
+ * passed the copy.  MORPH_E_INVAL for null pointers with bytes > 0;
+ * MORPH_E_HIP if the copy cannot be queued. */
+int morph_copy_async(void *dst, const void *src, size_t bytes, morph_stream_t stream);
 
 /* ---- packed bitmaps ----------------------------------------------------- */
 /*

@@ -28,7 +28,7 @@ import torch
 
 __all__ = [
     "Bitmap", "RLE", "MorphError", "se", "OPS",
-    "morph_version", "morph_strerror", "morph_last_hip_error",
+    "morph_version", "morph_strerror", "morph_last_hip_error", "morph_copy_async",
     "morph_erode_rect_packed", "morph_dilate_rect_packed", "morph_open_rect_packed",
     "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
@@ -107,6 +107,7 @@ def _load():
         "morph_version": (ctypes.c_char_p, []),
         "morph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "morph_last_hip_error": (ctypes.c_char_p, []),
+        "morph_copy_async": (ctypes.c_int, [P, P, SZ, P]),
         "morph_pack_to_rle": (ctypes.c_int, [RL, BM, P, SZ, P]),
         "morph_rle_to_pack": (ctypes.c_int, [BM, RL, P]),
         "morph_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, SE]),
@@ -338,6 +339,13 @@ def morph_pack_to_rle(dst: RLE, src: Bitmap, ws=None, stream=None):
     p, n = _ws(ws)
     _check(_lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(r), p, n, _stream(stream)),
            "morph_pack_to_rle")
+
+
+def morph_copy_async(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):
+    """Asynchronous copy of nbytes between device or pinned host addresses
+    (integers, e.g. tensor.data_ptr()) on `stream`."""
+    _check(_lib.morph_copy_async(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes, _stream(stream)),
+           "morph_copy_async")
 
 
 def morph_rle_to_pack(dst: Bitmap, src: RLE, stream=None):

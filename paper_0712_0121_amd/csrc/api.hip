@@ -231,6 +231,15 @@ extern "C" {
 
 const char *morph_version(void) { return "morph 0.1 (gfx950, HIP)"; }
 
+int morph_copy_async(void *dst, const void *src, size_t bytes, morph_stream_t stream)
+{
+    if (bytes == 0) return MORPH_OK;
+    if (!dst || !src) return MORPH_E_INVAL;
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 const char *morph_strerror(int code)
 {
     switch (code) {

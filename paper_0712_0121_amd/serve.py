@@ -228,6 +228,12 @@ class GpuExecutor:
         # (Server(keep_results=False)), since a kept result is a view of one
         self.recycle = recycle_outputs
         self.out_pool = collections.defaultdict(list)
+        # events are reused: a new one costs about 80 us of host time at its
+        # first record, a recorded one about 5.  Each goes back once: an
+        # upload's after the compute stream's wait on it is queued (a wait
+        # binds to the record at that moment), a launch's once it has been
+        # seen complete, a download's at release
+        self.ev_pool = []
         # device buffer pairs per page shape, each with its batch descriptors
         # per chain; a pair goes back on release once the request's download
         # has completed (every upload, launch and copy on it is then done), so
@@ -238,6 +244,9 @@ class GpuExecutor:
 
     def footprint(self, r: Request) -> int:
         return 2 * r.H * ((r.W + 63) // 64) * 8
+
+    def _event(self):
+        return self.ev_pool.pop() if self.ev_pool else self.torch.cuda.Event()
 
     def trim(self):
         """Drops the pooled device buffer pairs and pinned result buffers,
@@ -261,12 +270,18 @@ class GpuExecutor:
         # a request alone on the device has nothing to overlap with: its
         # copies go on the compute stream, which saves two cross-stream waits
         up = self.compute if r.alone else self.copy
-        with torch.cuda.stream(up):
-            a.words.copy_(host[:, : a.stride], non_blocking=True)
-            ev = None
-            if up is not self.compute:
-                ev = torch.cuda.Event()
-                ev.record(up)
+        if host.is_pinned() and host.is_contiguous() and host.shape[1] == a.stride:
+            # pooled buffers and a pinned page that lives as long as the
+            # request: the library's plain copy, without the framework's
+            # per-copy bookkeeping
+            M.morph_copy_async(a.words.data_ptr(), host.data_ptr(), a.words.numel() * 8, up)
+        else:
+            with torch.cuda.stream(up):
+                a.words.copy_(host[:, : a.stride], non_blocking=True)
+        ev = None
+        if up is not self.compute:
+            ev = self._event()
+            ev.record(up)
         # the chain's batch descriptors, built once: operation k reads the
         # buffer written by operation k-1
         key = tuple(r.chain)
@@ -284,6 +299,7 @@ class GpuExecutor:
             st = r.state
             if st.get("up") is not None:
                 self.compute.wait_event(st["up"])
+                self.ev_pool.append(st["up"])
                 st["up"] = None
             items.append(st["descs"][r.pos])
         if len(items) <= self.direct_max:
@@ -291,7 +307,7 @@ class GpuExecutor:
                 for r in reqs:
                     op, se = r.chain[r.pos]
                     M.PACKED[op](r.state["nxt"], r.state["cur"], se, self.ws)
-                ev = torch.cuda.Event()
+                ev = self._event()
                 ev.record(self.compute)
             for r in reqs:
                 r.state["ev"] = ev
@@ -301,7 +317,7 @@ class GpuExecutor:
         if self.staging_ev[k] is not None:
             self.staging_ev[k].synchronize()       # its copy has been consumed
         M.morph_batch_launch(items, self.ws, self.staging[k], stream=self.compute)
-        ev = torch.cuda.Event()
+        ev = self._event()
         ev.record(self.compute)
         self.staging_ev[k] = ev
         for r in reqs:
@@ -309,7 +325,14 @@ class GpuExecutor:
         return ev
 
     def done(self, token) -> bool:
-        return token.query()
+        if not token.query():
+            return False
+        # complete: its staging copy has been consumed too
+        for i, e in enumerate(self.staging_ev):
+            if e is token:
+                self.staging_ev[i] = None
+        self.ev_pool.append(token)
+        return True
 
     def error(self, token):
         return None
@@ -325,12 +348,13 @@ class GpuExecutor:
         pool = self.out_pool[shape] if self.recycle else None
         out = pool.pop() if pool else torch.empty(shape, dtype=torch.int64, pin_memory=True)
         down = self.compute if r.alone else self.down
-        with torch.cuda.stream(down):
-            if down is not self.compute:
-                down.wait_event(st["ev"])
-            out.copy_(st["cur"].words, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(down)
+        if down is not self.compute:
+            down.wait_event(st["ev"])
+        # out is pinned and pooled, the device pair too: neither is freed
+        # before this copy's event has been seen complete
+        self.M.morph_copy_async(out.data_ptr(), st["cur"].words.data_ptr(), out.numel() * 8, down)
+        ev = self._event()
+        ev.record(down)
         st["out"], st["down"] = out, ev
 
     def downloaded(self, r: Request) -> bool:
@@ -343,8 +367,15 @@ class GpuExecutor:
         st = r.state
         out, down, pair = st.get("out"), st.get("down"), st.get("pair")
         finished = down is not None and down.query()
+        if down is not None and not finished:
+            # a failed request's result copy may still be in flight, and the
+            # framework does not know of it: wait before its pinned buffer
+            # can be freed and handed out again
+            down.synchronize()
         if self.recycle and out is not None and finished:
             self.out_pool[tuple(out.shape)].append(out)
+        if down is not None:
+            self.ev_pool.append(down)
         if pair is not None:
             if finished:
                 self.buf_pool[(r.W, r.H)].append(pair)

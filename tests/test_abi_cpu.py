@@ -44,6 +44,14 @@ def test_version_and_strerror():
     assert M.morph_strerror(-99) == "unknown error"
 
 
+def test_copy_async_argument_checks():
+    # checked before any HIP call: nothing to copy, or a null pointer
+    assert M._lib.morph_copy_async(None, None, 0, None) == 0
+    buf = ctypes.create_string_buffer(16)
+    assert M._lib.morph_copy_async(None, ctypes.addressof(buf), 8, None) == -1
+    assert M._lib.morph_copy_async(ctypes.addressof(buf), None, 8, None) == -1
+
+
 def test_sizes():
     assert M.morph_rle_max_runs(2550, 3300) == 3300 * 1275
     assert M.morph_rle_max_runs(1, 1) == 1
