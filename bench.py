@@ -203,8 +203,9 @@ def bench_serving(M, dev, seconds):
     """Serving: Poisson arrivals of pages sized as in the mixed batch, each with
     the chain close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5, under a 64 GB
     HBM budget; served (continuous batching) vs plain per-page path on the
-    same trace.  Plain saturation: a burst of requests at time 0; served
-    saturation: completions per second under a Poisson stream above it."""
+    same trace.  Plain saturation: a burst of requests at time 0 (it serves
+    one page at a time); served saturation: the highest Poisson arrival rate
+    it keeps up with, by bisection."""
     import torch
     import pagegen
     from paper_0712_0121_amd import serve
@@ -246,20 +247,30 @@ def bench_serving(M, dev, seconds):
             t = time.perf_counter()
             serve.run_trace_served(srv, burst, np.zeros(len(burst)))
             p1_burst = len(burst) / (time.perf_counter() - t)
-    # sustained served capacity: a Poisson stream above it for 2 s, counting
-    # completions per second (a burst forms larger batches than arrivals do).
-    # Measured twice and the lower kept: the served path is host-bound near
-    # its capacity, and a high estimate puts the 0.9x point past it
-    p1_runs = []
-    for rep in range(2):
-        arrivals = pagegen.poisson_trace(1.5 * p1_burst, 2.0, seed=5002 + rep)
-        sustained = reqs(len(arrivals))
+    # served saturation: the highest Poisson arrival rate the served path
+    # keeps up with (p99 under 20 ms over a 1.5 s trace), by bisection
+    # between the plain saturation and 1.3x the burst rate.  The completion
+    # rate under overload overstates it: an overloaded server forms larger
+    # batches than arrivals at 90 % of capacity do
+    def sustained(rate, seed):
+        arrivals = pagegen.poisson_trace(rate, 1.5, seed=seed)
+        rq = reqs(len(arrivals))
         with _frozen_requests():
             srv = serve.Server(ex, budget, keep_results=False)
-            serve.run_trace_served(srv, sustained, arrivals, timeout=120)
-        p1_runs.append(serve.latency_stats(srv.completed, 0.0)["pages_per_s"])
-        del sustained, srv
-    p1 = min(p1_runs)
+            serve.run_trace_served(srv, rq, arrivals, timeout=120)
+        st = serve.latency_stats(srv.completed, 0.0)
+        return st["p99_ms"] < 20.0, st["p99_ms"]
+    lo, hi = p0, 1.3 * p1_burst
+    probes = []
+    for k in range(5):
+        mid = 0.5 * (lo + hi)
+        ok, p99 = sustained(mid, 5002 + k)
+        probes.append({"qps": mid, "p99_ms": p99, "kept_up": ok})
+        if ok:
+            lo = mid
+        else:
+            hi = mid
+    p1 = lo
     points = []
     for name, qps in (("0.5x plain saturation", 0.5 * p0), ("0.9x plain saturation", 0.9 * p0),
                       ("0.9x served saturation", 0.9 * p1)):
@@ -286,7 +297,8 @@ def bench_serving(M, dev, seconds):
             "seconds_per_trace": seconds,
             "device_only_ms": {"n": int(len(dev_ms)), "p50": float(np.percentile(dev_ms, 50)),
                                "p99": float(np.percentile(dev_ms, 99)), "max": float(dev_ms.max())},
-            "saturation_pages_s": {"plain": p0, "served": p1, "served_runs": p1_runs, "served_burst": p1_burst},
+            "saturation_pages_s": {"plain": p0, "served": p1, "served_burst": p1_burst},
+            "served_saturation_probes": probes,
             "load_points": points}
 
 

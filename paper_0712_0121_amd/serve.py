@@ -80,7 +80,7 @@ class Server:
         self.pending = collections.deque()
         self.active = []
         self.batches = collections.deque()     # (token, [requests])
-        self.downloading = []
+        self.downloading = collections.deque()
         self.completed = []
         self.failed = []
         self.launches = 0
@@ -131,25 +131,31 @@ class Server:
         # downloads finish in the order they were queued when the executor
         # says so (one copy stream): then polling stops at the first one
         # still in flight
+        # (a deque taken from the front: a step costs the same however many
+        # downloads are queued, which keeps a queue from slowing the loop
+        # that has to drain it)
         in_order = getattr(self.ex, "downloads_in_order", False)
-        still = []
-        for k, r in enumerate(self.downloading):
-            if r.error is not None:
-                continue
-            if self.ex.downloaded(r):
-                res = self.ex.finish(r)
-                r.result = res if self.keep_results else None
-                r.t_done = self.now()
-                self.ex.release(r)
-                self.used -= self.ex.footprint(r)
-                self.completed.append(r)
-                moved = True
-            elif in_order:
-                still.extend(x for x in self.downloading[k:] if x.error is None)
-                break
-            else:
-                still.append(r)
-        self.downloading = still
+        if in_order:
+            q = self.downloading
+            while q:
+                r = q[0]
+                if r.error is None and not self.ex.downloaded(r):
+                    break
+                q.popleft()
+                if r.error is None:
+                    self._complete(r)
+                    moved = True
+        else:
+            still = collections.deque()
+            for r in self.downloading:
+                if r.error is not None:
+                    continue
+                if self.ex.downloaded(r):
+                    self._complete(r)
+                    moved = True
+                else:
+                    still.append(r)
+            self.downloading = still
         # admission, first come first served
         while self.pending and self.used + self.ex.footprint(self.pending[0]) <= self.budget:
             r = self.pending.popleft()
@@ -176,15 +182,26 @@ class Server:
                 return True
             self.batches.append((token, ready))
             self.launches += 1
+            done_chain = False
             for r in ready:
                 self.ex.advance(r)
                 r.pos += 1
                 if r.pos == len(r.chain):
-                    self.active.remove(r)
+                    done_chain = True
                     self.ex.begin_download(r)
                     self.downloading.append(r)
+            if done_chain:
+                self.active = [r for r in self.active if r.pos < len(r.chain)]
             moved = True
         return moved
+
+    def _complete(self, r: Request):
+        res = self.ex.finish(r)
+        r.result = res if self.keep_results else None
+        r.t_done = self.now()
+        self.ex.release(r)
+        self.used -= self.ex.footprint(r)
+        self.completed.append(r)
 
     def idle(self) -> bool:
         return not (self.pending or self.active or self.batches or self.downloading)
