@@ -69,8 +69,14 @@ class Server:
     docstring).  Call submit() as requests arrive and step() in a loop."""
 
     def __init__(self, executor, budget_bytes: int, max_inflight_batches: int = 4,
-                 clock=time.perf_counter, keep_results: bool = True):
+                 clock=time.perf_counter, keep_results: bool = True, min_batch: int = 8):
         self.ex = executor
+        # with two launches queued, the next one waits until min_batch
+        # requests are ready (with fewer queued it goes at once, so a lone
+        # request still has its chain queued behind the device's work):
+        # each launch costs the host about as much as several pages'
+        # bookkeeping, and at high load tiny launches cap the pages per second
+        self.min_batch = max(1, int(min_batch))
         self.keep_results = keep_results
         self.budget = int(budget_bytes)
         self.max_batches = max_inflight_batches
@@ -174,6 +180,8 @@ class Server:
         # alone has its whole chain queued at once and later arrivals join
         # the next launch at their own position
         while self.active and len(self.batches) < self.max_batches:
+            if len(self.batches) >= 2 and len(self.active) < self.min_batch:
+                break
             ready = list(self.active)
             try:
                 token = self.ex.launch(ready)
