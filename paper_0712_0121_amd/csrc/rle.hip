@@ -1275,12 +1275,56 @@ __device__ __forceinline__ int2 mask_cand(const MaskRunX &t, const int2 *R, int 
     return make_int2(max(0, s - t.dx), min(t.W, e - t.dx - t.len + 1));
 }
 
+// Intersection of the accumulated row A (na runs) with the candidates of
+// the source row (nb of them, ascending starts and ends, dead ones with
+// s >= e skipped), lanes over A: bisection for the first candidate ending
+// after each run's start, the overlaps counted, a group scan, then emitted.
+template <class GetB>
+__device__ __forceinline__ int mask_intersect(const int2 *A, int na, int nb, GetB getB, int2 *o,
+                                              long long cap_row)
+{
+    const int gl = glane();
+    int carry = 0;
+    for (int k0 = 0; k0 < na; k0 += kGroup) {
+        const int k = k0 + gl;
+        int c = 0, span = 0, j0 = 0, sa = 0, ea = 0;
+        if (k < na) {
+            const int2 a = A[k];
+            sa = a.x;
+            ea = a.y;
+            int lo = 0, hi = nb;            // the first candidate that ends after sa
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (getB(mid).y > sa) hi = mid; else lo = mid + 1;
+            }
+            j0 = lo;
+            for (int j = j0; j < nb; j++) {
+                const int2 b = getB(j);
+                if (b.x >= ea) break;
+                span++;
+                c += live(b) ? 1 : 0;
+            }
+        }
+        const int inc = group_incl_scan(c);
+        int idx = carry + inc - c;
+        for (int j = j0; j < j0 + span; j++) {
+            const int2 b = getB(j);
+            if (!live(b)) continue;
+            if (idx < cap_row) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
+            idx++;
+        }
+        carry += group_last(inc);
+    }
+    return carry;
+}
+
 __global__ __launch_bounds__(256) void mask_and_kernel(RowsIn src, int P, int H, MaskRunX t, int first,
                                                        const int *__restrict__ acc_cnt,
                                                        const int *__restrict__ acc_runs, long long cap_row,
                                                        int *__restrict__ out_cnt, int *__restrict__ out_runs,
                                                        unsigned long long *trace)
 {
+    __shared__ int2 stage[kGroupsPerBlock][kStageRuns];
     const long long r = (long long)xcd_block() * kGroupsPerBlock + (threadIdx.x >> 4);
     if (r >= (long long)P * H) return;      // whole group
     const int gl = glane();
@@ -1308,35 +1352,17 @@ __global__ __launch_bounds__(256) void mask_and_kernel(RowsIn src, int P, int H,
     } else {
         const int2 *A = reinterpret_cast<const int2 *>(acc_runs) + r * cap_row;
         const int na = min(max(acc_cnt[r], 0), (int)cap_row);
-        for (int k0 = 0; k0 < na; k0 += kGroup) {
-            const int k = k0 + gl;
-            int c = 0, span = 0, j0 = 0, sa = 0, ea = 0;
-            if (k < na) {
-                const int2 a = A[k];
-                sa = a.x;
-                ea = a.y;
-                int lo = 0, hi = nb;        // the first candidate that ends after sa
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (candB(mid).y > sa) hi = mid; else lo = mid + 1;
-                }
-                j0 = lo;
-                for (int j = j0; j < nb; j++) {
-                    const int2 b = candB(j);
-                    if (b.x >= ea) break;
-                    span++;
-                    c += live(b) ? 1 : 0;
-                }
-            }
-            const int inc = group_incl_scan(c);
-            int idx = carry + inc - c;
-            for (int j = j0; j < j0 + span; j++) {
-                const int2 b = candB(j);
-                if (!live(b)) continue;
-                if (idx < cap_row) o[idx] = make_int2(max(sa, b.x), min(ea, b.y));
-                idx++;
-            }
-            carry += group_last(inc);
+        if (na == 0) {
+            carry = 0;                      // nothing left to intersect (erosion empties rows fast)
+        } else if (nb <= kStageRuns) {
+            // the source row's candidates computed once into this group's
+            // LDS window: the bisections then read LDS, not global memory
+            int2 *sB = stage[threadIdx.x >> 4];
+            for (int k = gl; k < nb; k += kGroup) sB[k] = candB(k);
+            wave_lds_sync();
+            carry = mask_intersect(A, na, nb, [&](int j) { return sB[j]; }, o, cap_row);
+        } else {
+            carry = mask_intersect(A, na, nb, candB, o, cap_row);
         }
     }
     if (gl == 0) {
