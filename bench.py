@@ -249,9 +249,10 @@ def bench_serving(M, dev, seconds):
             p1_burst = len(burst) / (time.perf_counter() - t)
     # served saturation: the highest Poisson arrival rate the served path
     # keeps up with (p99 under 20 ms over a 1.5 s trace), by bisection
-    # between the plain saturation and 1.3x the burst rate.  The completion
-    # rate under overload overstates it: an overloaded server forms larger
-    # batches than arrivals at 90 % of capacity do
+    # between the plain saturation and 1.5x the larger of it and the burst
+    # rate (the burst rate alone varies too much to bound the search).  The
+    # completion rate under overload overstates it: an overloaded server
+    # forms larger batches than arrivals at 90 % of capacity do
     def sustained(rate, seed):
         arrivals = pagegen.poisson_trace(rate, 1.5, seed=seed)
         rq = reqs(len(arrivals))
@@ -260,7 +261,7 @@ def bench_serving(M, dev, seconds):
             serve.run_trace_served(srv, rq, arrivals, timeout=120)
         st = serve.latency_stats(srv.completed, 0.0)
         return st["p99_ms"] < 20.0, st["p99_ms"]
-    lo, hi = p0, 1.3 * p1_burst
+    lo, hi = p0, 1.5 * max(p0, p1_burst)
     probes = []
     for k in range(5):
         mid = 0.5 * (lo + hi)
@@ -298,6 +299,8 @@ def bench_serving(M, dev, seconds):
             "device_only_ms": {"n": int(len(dev_ms)), "p50": float(np.percentile(dev_ms, 50)),
                                "p99": float(np.percentile(dev_ms, 99)), "max": float(dev_ms.max())},
             "saturation_pages_s": {"plain": p0, "served": p1, "served_burst": p1_burst},
+            # false when every probe held: "served" is then only a lower bound
+            "served_saturation_bounded": any(not q["kept_up"] for q in probes),
             "served_saturation_probes": probes,
             "load_points": points}
 
