@@ -639,6 +639,25 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same step captured once into a HIP graph and replayed (no entry
+    # point allocates, synchronises or records a memset); its outputs must
+    # equal the eager step's byte for byte
+    graph_check = {}
+    outs = lambda: (dst.words, back.words, rle_src.row_ptr, rle_src.runs, rle_dst.row_ptr, rle_dst.runs)
+    eager_out = [t.clone() for t in outs()]
+    g_step = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_step):
+        step()
+    for _ in range(args.warmup):
+        g_step.replay()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for s in range(args.steps):
+        g_step.replay()
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - tg
+    graph_check["identical"] = all(bool(torch.equal(a, b)) for a, b in zip(eager_out, outs()))
+    del g_step, eager_out
     # the same steps again, with HIP events around every operation and the
     # library's launch tracing, for the per-operation and per-kernel figures
     evs = [new_events() for _ in range(args.steps)]
@@ -678,6 +697,7 @@ def main():
         "value": px_step / (dt / args.steps) / 1e9,
         "unit": "Gpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "ms_per_step_graph": dt_graph * 1e3 / args.steps, "graph_outputs_identical": graph_check["identical"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+i32",
         "data": "synthetic (seeded letter pages, %d distinct, resident in HBM)" % args.distinct,
         "config": {"workload": "letter page 2550x3300 (40 words/row), batch of %d pages; erode, dilate, "
