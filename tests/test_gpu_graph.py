@@ -1,9 +1,12 @@
-"""The single-page workload (bitmap -> runs, the letter cases on runs, runs
--> bitmap, and the same cases on the bitmap) captured once into a HIP graph
-and replayed: every replay, with the program's own eager work and
-synchronisations between replays, gives every output exactly as the eager
-calls do.  None of these entry points allocates, copies to the host,
-synchronises or records a memset, so all of their launches can be captured."""
+"""The letter workload (bitmap -> runs, the letter cases on runs, runs ->
+bitmap, and the same cases on the bitmap), on one page and on a stack of 12
+pages, captured once into a HIP graph and replayed: every replay, with the
+program's own eager work and synchronisations between replays, gives every
+output exactly as the eager calls do.  None of these entry points
+allocates, copies to the host, synchronises or records a memset, so all of
+their launches can be captured.  The stack (39 600 rows) takes the
+multi-block scans and, for the tall elements, the block scans along the
+columns, which a single page does not reach."""
 import numpy as np
 import pytest
 import torch
@@ -21,21 +24,22 @@ def lib():
     require_gpu()
 
 
-def test_page_workload_graph_replays_match_eager():
+@pytest.mark.parametrize("npages", [1, 12])
+def test_workload_graph_replays_match_eager(npages):
     import paper_0712_0121_amd as M
-    page = pagegen.letter_page(2000)
-    W, H = page.W, page.H
-    src = M.Bitmap.from_words(page.words(), W)
+    pages = [pagegen.letter_page(2000 + i) for i in range(npages)]
+    W, H = pages[0].W, pages[0].H
+    src = M.Bitmap.from_words(np.concatenate([p.words() for p in pages]), W, npages=npages)
     jobs = [(op, se) for se in SES for op in pagegen.OPS]
-    pk_out = [M.Bitmap.empty(W, H) for _ in jobs]
-    rl_out = [M.RLE.empty(W, H) for _ in jobs]
-    r_in = M.RLE.empty(W, H)
-    back = M.Bitmap.empty(W, H)
-    ws_p = torch.empty(max([1] + [M.morph_workspace_bytes(op, 0, W, H, se) for op, se in jobs]),
+    pk_out = [M.Bitmap.empty(W, H, npages) for _ in jobs]
+    rl_out = [M.RLE.empty(W, H, npages) for _ in jobs]
+    r_in = M.RLE.empty(W, H, npages)
+    back = M.Bitmap.empty(W, H, npages)
+    ws_p = torch.empty(max([1] + [M.morph_workspace_bytes(op, 0, W, H * npages, se) for op, se in jobs]),
                        dtype=torch.uint8, device="cuda")
-    ws_r = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, 1, se) for op, se in jobs),
+    ws_r = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, npages, se) for op, se in jobs),
                        dtype=torch.uint8, device="cuda")
-    ws_c = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H), dtype=torch.uint8, device="cuda")
+    ws_c = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * npages), dtype=torch.uint8, device="cuda")
 
     def workload():
         M.morph_pack_to_rle(r_in, src, ws_c)
@@ -61,13 +65,16 @@ def test_page_workload_graph_replays_match_eager():
             r.runs.fill_(-7)
         torch.cuda.synchronize()
 
-    workload()
+    with M.Trace() as tr:
+        workload()
     want = snapshot()
+    scans = tr.result.get("col_scan_kernel", {"launches": 0})["launches"]
+    assert (scans > 0) == (npages > 1), "block scans along the columns: %d launches" % scans
     poison()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         workload()
-    other = M.Bitmap.empty(W, H)
+    other = M.Bitmap.empty(W, H, npages)
     for rep in range(3):
         poison()
         g.replay()
