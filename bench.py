@@ -51,6 +51,16 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    g = ap.add_argument_group("profile summary (no GPU): rocprofv3 CSV output -> markdown")
+    g.add_argument("--summarize-profile", action="store_true")
+    g.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output directory")
+    g.add_argument("--fetch-dir", help="rocprofv3 --pmc FETCH_SIZE output directory")
+    g.add_argument("--write-dir", help="rocprofv3 --pmc WRITE_SIZE output directory")
+    g.add_argument("--calib-bytes", type=int, default=256 * LETTER_H * 40 * 8,
+                   help="bytes the calibration copy reads and writes")
+    g.add_argument("--title", default="Kernel time and HBM traffic: letter-page workload, 256 pages")
+    g.add_argument("--cmd", action="append", help="profiling command to list in the summary")
+    g.add_argument("--out", help="markdown file to write")
     return ap.parse_args()
 
 
@@ -116,6 +126,136 @@ def profiled_traffic(kernel):
                 return None
             return float(kv["bytes_per_launch"]) if cur == kv["sha256_16"] else None
     return None
+
+
+# Kernels whose HBM traffic bench.py reports, with the source file that
+# builds each (the traffic figure is used only while that file is unchanged).
+TRAFFIC_SOURCES = {
+    "rect_kernel": "paper_0712_0121_amd/csrc/packed.hip",
+    "col_and_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "row_erode_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "pack_rows_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "col_scan_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "pack_to_rle_group_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "rle_to_pack_group_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+}
+# The calibration kernel: torch's elementwise bitwise_or of the batch with 0
+# (a plain copy of known size), picked by the functor in its full name so
+# that no other elementwise kernel (clones, compares) enters the scale.
+CALIB_TAG = "BitwiseOrFunctor"
+
+
+def short_kernel_name(name):
+    """'void col_and_kernel<false>(RowsIn, int, ...)' -> 'col_and_kernel'."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    depth, out = 0, []
+    for ch in n:
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            break
+        elif depth == 0:
+            out.append(ch)
+    n = "".join(out).strip()
+    return n.split("::")[-1] if n.startswith("morph::") else n
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit("no *%s under %s" % (suffix, directory))
+    return rows
+
+
+def _per_dispatch(rows, counter):
+    """{dispatch id: (kernel name, summed counter value)} for one counter."""
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        d = r["Dispatch_Id"]
+        name, v = out.get(d, (r["Kernel_Name"], 0.0))
+        out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def summarize_profile(args):
+    """Writes the markdown kernel-time and HBM-traffic summary from the CSV
+    output of one rocprofv3 --kernel-trace --stats run and one --pmc run each
+    for FETCH_SIZE and WRITE_SIZE (KiB per dispatch).  Counter values are
+    scaled to bytes by what the same counters read for the calibration copy
+    (CALIB_TAG dispatches, calib_bytes read and written each)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    lines = ["# %s" % args.title, "", "Commands (from the repository root, on one MI355X):", "", "```",
+             "export TMPDIR=/tmp"] + list(args.cmd or []) + [
+             "python3 bench.py --summarize-profile --trace-dir %s --fetch-dir %s --write-dir %s "
+             "--calib-bytes %d --out %s" % (args.trace_dir, args.fetch_dir, args.write_dir, args.calib_bytes,
+                                             args.out), "```", ""]
+    if args.trace_dir:
+        stats = _csv_rows(args.trace_dir, "_kernel_stats.csv")
+        tot = sum(float(r["TotalDurationNs"]) for r in stats)
+        lines += ["## rocprofv3 --kernel-trace --stats", "", "| kernel | calls | total ms | average us | % |",
+                  "|---|---|---|---|---|"]
+        grouped = {}
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+            name = r["Name"] if len(r["Name"]) <= 100 else r["Name"][:100] + "..."
+            lines.append("| %s | %s | %.2f | %.1f | %.1f |" % (name.replace("|", "/"), r["Calls"],
+                                                                 float(r["TotalDurationNs"]) / 1e6,
+                                                                 float(r["AverageNs"]) / 1e3,
+                                                                 100.0 * float(r["TotalDurationNs"]) / tot))
+            k = short_kernel_name(r["Name"])
+            c, t = grouped.get(k, (0, 0.0))
+            grouped[k] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
+        lines += ["", "Per kernel, all template instances together (calls, average us): " +
+                  "; ".join("%s %d, %.1f" % (k, c, t / c / 1e3) for k, (c, t) in
+                            sorted(grouped.items(), key=lambda kv: -kv[1][1]) if k in TRAFFIC_SOURCES), ""]
+    fetch = _per_dispatch(_csv_rows(args.fetch_dir, "_counter_collection.csv"), "FETCH_SIZE")
+    write = _per_dispatch(_csv_rows(args.write_dir, "_counter_collection.csv"), "WRITE_SIZE")
+    cal_f = [v for n, v in fetch.values() if CALIB_TAG in n]
+    cal_w = [v for n, v in write.values() if CALIB_TAG in n]
+    if not cal_f or not cal_w:
+        raise SystemExit("no %s dispatch in the counter runs" % CALIB_TAG)
+    kib_f, kib_w = sum(cal_f) / len(cal_f), sum(cal_w) / len(cal_w)
+    sf, sw = args.calib_bytes / (kib_f * 1024.0), args.calib_bytes / (kib_w * 1024.0)
+
+    def by_kernel(d):
+        g = {}
+        for n, v in d.values():
+            g.setdefault(short_kernel_name(n), []).append(v)
+        return g
+    gf, gw = by_kernel(fetch), by_kernel(write)
+    lines += ["## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE; per-dispatch means)", "",
+              "Scaling: the calibration copy (%d dispatch(es) whose name contains `%s`, %d bytes read and "
+              "written each) reads FETCH_SIZE %.0f KiB and WRITE_SIZE %.0f KiB, so FETCH_SIZE x %.3f and "
+              "WRITE_SIZE x %.3f give bytes." % (len(cal_f), CALIB_TAG, args.calib_bytes, kib_f, kib_w, sf, sw),
+              "", "| kernel | launches | read MB / launch | written MB / launch |", "|---|---|---|---|"]
+    traffic = {}
+    for k in sorted(set(gf) | set(gw), key=lambda k: -(sum(gf.get(k, [0])) + sum(gw.get(k, [0])))):
+        f = gf.get(k, [0.0])
+        w = gw.get(k, [0.0])
+        rb = sum(f) / len(f) * 1024.0 * sf
+        wb = sum(w) / len(w) * 1024.0 * sw
+        lines.append("| %s | %d | %.1f | %.1f |" % (k, max(len(f), len(w)), rb / 1e6, wb / 1e6))
+        traffic[k] = rb + wb
+    lines += ["", "Machine-read lines (bench.py reports `traffic` from these while the kernel source is "
+              "unchanged):", ""]
+    for k, src in TRAFFIC_SOURCES.items():
+        if k in traffic:
+            h = hashlib.sha256(open(os.path.join(root, src), "rb").read()).hexdigest()[:16]
+            lines.append("traffic %s bytes_per_launch=%.0f source=%s sha256_16=%s" % (k, traffic[k], src, h))
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", args.out)
 
 
 def time_ms(fn, reps=5):
@@ -556,6 +696,9 @@ def bench_repr(M, dev, tuner):
 
 def main():
     args = parse()
+    if args.summarize_profile:
+        summarize_profile(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (run --gpus 1)" % args.gpus,
               file=sys.stderr)

@@ -30,7 +30,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import apply as rect_apply, rle_decode, rle_encode
-from .transpose import from_lines, to_lines, transpose_lines
+from .transpose import from_lines, rle_transpose, to_lines
 
 
 def run_histograms(lines, W: int):
@@ -150,7 +150,7 @@ def layout_boxes(pages, W: int, num: int, den: int, connectivity: int = 8):
     vb = np.zeros(H + 1, dtype=np.int64)
     for lines in pages:
         hb += run_histograms(lines, W)[1]
-        vb += run_histograms(transpose_lines(lines, W), H)[1]
+        vb += run_histograms(to_lines(*rle_transpose(*from_lines(lines), W, H)), H)[1]
     gx = histogram_percentile(hb, num, den)
     gy = histogram_percentile(vb, num, den)
     se = (gx + 1, gy + 1, (gx + 1) // 2, (gy + 1) // 2)

@@ -8,8 +8,8 @@ description of what each step computes:
   complement, one-dimensional opening/closing as deletion of short runs/gaps,
   one-dimensional erosion as shrinking runs and dilation by complementation;
 * between-line boolean operations (section "Between Line Boolean
-  Operations"): an ordered merge of the transitions of two lines, fed to a
-  sink that reassembles intervals;
+  Operations"): the combined value of two lines at every run boundary of
+  either, fed in ascending order to a sink that reassembles intervals;
 * the logarithmic decomposition of a line structuring element applied
   between lines (section "Efficient Binary Decompositions").
 
@@ -21,9 +21,6 @@ whole project: outside the line, pixels count as 1 for erosion and 0 for
 dilation.
 """
 from __future__ import annotations
-
-BIG = 1 << 62          # the value an exhausted transition source reports
-
 
 # ------------------------------------------------------------ within a line
 def complement(runs, W):
@@ -111,32 +108,24 @@ class TransitionSink:
             self._open = None
 
 
-def transitions(runs, offset=0):
-    """Transitions of a line in ascending order: (start, True), (end, False)."""
-    for s, e in runs:
-        yield s + offset, True
-        yield e + offset, False
+def _covers(line, x):
+    """Whether pixel x lies in one of the line's runs."""
+    return any(s <= x < e for s, e in line)
 
 
 def line_merge(l1, l2, combine, offset2=0):
-    """Ordered merge of the transitions of two lines (the second shifted by
-    offset2); after each transition the sink receives combine(b1, b2) of
-    the two current pixel states."""
-    t1 = list(transitions(l1))
-    t2 = list(transitions(l2, offset2))
-    i = j = 0
-    b1 = b2 = False
+    """A boolean combination of two lines (the second shifted by offset2),
+    from the definition: the combined line can only change value where one
+    of the two lines does, so it is constant between consecutive run
+    boundaries of either line.  At every boundary coordinate x (in
+    ascending order) the sink receives combine(pixel x in line 1, pixel x
+    in line 2), and it turns these values into the canonical runs."""
+    a = list(l1)
+    b = [(s + offset2, e + offset2) for s, e in l2]
+    cuts = sorted({x for s, e in a + b for x in (s, e)})
     sink = TransitionSink()
-    while i < len(t1) or j < len(t2):
-        c1 = t1[i][0] if i < len(t1) else BIG
-        c2 = t2[j][0] if j < len(t2) else BIG
-        if c1 < c2:
-            x, b1 = t1[i]
-            i += 1
-        else:
-            x, b2 = t2[j]
-            j += 1
-        sink.append(x, combine(b1, b2))
+    for x in cuts:
+        sink.append(x, combine(_covers(a, x), _covers(b, x)))
     return sink.runs
 
 

@@ -4,11 +4,9 @@ operations, in plain Python (test infrastructure only).
 * ``rle_transpose`` is the plain definition: decode the run-length image to
   pixels, swap the axes, re-encode (the "decompress and recode" method the
   section "Efficient Transpose" starts from).
-* ``transpose_lines`` is that section's simple algorithm written out: walk
-  the input lines in order and keep, for every output line, the input line
-  at which its current run opened; pixels outside the runs of the current
-  input line close the open runs, pixels inside them open runs that are not
-  open yet.  It shares nothing with ``rle_transpose`` and pins it.
+* ``transpose_lines`` works on run lists, one output line at a time: output
+  line k collects the ranges of consecutive input lines whose runs cover
+  pixel k.  It shares nothing with ``rle_transpose`` and pins it.
 * ``rect_rlet`` composes a rectangle operation from within-line operations
   and transposition (section "Run Length Image Coding", the erode2d
   composition; section "2D Morphological Operators for Rectangular Masks",
@@ -36,29 +34,27 @@ def rle_transpose(row_ptr, runs, W: int, H: int):
 
 
 def transpose_lines(lines, W: int):
-    """The simple transposition of a list of H lines of width W into W lines
-    of width H, pixel by pixel with an array of open runs."""
+    """Transposition of a list of H lines of width W into W lines of width
+    H, one output line at a time: output line k lists the maximal ranges of
+    consecutive input lines whose runs cover pixel k (a binary search over
+    each input line's run starts)."""
+    import bisect
     H = len(lines)
-    out = [[] for _ in range(W)]
-    opened = [None] * W                    # input line where the run of column k opened
-    for i, line in enumerate(lines):
-        last = 0
-        for s, e in line:
-            for k in range(last, s):       # white pixels of line i close open runs
-                if opened[k] is not None:
-                    out[k].append((opened[k], i))
-                    opened[k] = None
-            for k in range(s, e):          # black pixels open runs not yet open
-                if opened[k] is None:
-                    opened[k] = i
-            last = e
-        for k in range(last, W):
-            if opened[k] is not None:
-                out[k].append((opened[k], i))
-                opened[k] = None
-    for k in range(W):                     # runs still open reach the last line
-        if opened[k] is not None:
-            out[k].append((opened[k], H))
+    starts = [[s for s, _ in line] for line in lines]
+    out = []
+    for k in range(W):
+        runs, first = [], None
+        for i, line in enumerate(lines):
+            j = bisect.bisect_right(starts[i], k) - 1
+            covered = j >= 0 and k < line[j][1]
+            if covered and first is None:
+                first = i
+            elif not covered and first is not None:
+                runs.append((first, i))
+                first = None
+        if first is not None:
+            runs.append((first, H))
+        out.append(runs)
     return out
 
 

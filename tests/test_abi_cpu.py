@@ -309,3 +309,16 @@ def test_shift_argument_errors():
     assert SR(rle(a, 150, H, capd), rle(b, W, H, 10)) == -4
     need = M.morph_shift_rows_rle_workspace_bytes(H)
     assert need >= H * 4
+
+
+def test_rotation_rationals_closed_forms():
+    """tan(a/2) and sin(a) as rationals over den: a = 90 degrees gives
+    tan 45 = sin 90 = 1; a = 60 degrees gives tan 30 = 1/sqrt(3) and
+    sin 60 = sqrt(3)/2; a = 0 gives 0; the pair is odd in a."""
+    den = 1 << 16
+    assert M.rotation_rationals(np.pi / 2, den) == (den, den, den)
+    assert M.rotation_rationals(np.pi / 3, den) == (round(den / np.sqrt(3)), round(den * np.sqrt(3) / 2), den)
+    assert M.rotation_rationals(0.0, den) == (0, 0, den)
+    t, s, _ = M.rotation_rationals(0.4, den)
+    assert M.rotation_rationals(-0.4, den) == (-t, -s, den)
+    assert M.rotation_rationals(np.pi / 2, 1000) == (1000, 1000, 1000)

@@ -1,6 +1,8 @@
 """GPU parity of line shifts, skews, rotation by skews and line operations at
 a slope against the oracle, on packed images (words, pad bits 0) and
 run-length images (row_ptr and runs exactly)."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -92,7 +94,9 @@ def test_skews_match_oracle(slope):
 @pytest.mark.parametrize("angle", [0.0, 0.1, -0.35, 0.7, np.pi / 2], ids=lambda a: "%.2f" % a)
 def test_rotation_matches_oracle(angle):
     img = blobs_img(7, 80, 120, 0.4)
-    tn, sn, den = M.rotation_rationals(angle)
+    # tan(a/2) and sin(a) over 2^16, computed here and not by the binding
+    den = 1 << 16
+    tn, sn = int(round(math.tan(angle / 2) * den)), int(round(math.sin(angle) * den))
     want = osh.rotate(img, tn, sn, den)
     pk, rl = both(img)
     assert_img(M.rotate(pk, tn, sn, den), want, "packed %.2f" % angle)

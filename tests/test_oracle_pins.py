@@ -752,3 +752,70 @@ def test_line_op_horizontal_is_the_rectangle_and_diagonal_by_hand():
     single[4, 4] = 1
     di = osh.line_op("dilate", single, 3, 1, 1)
     assert [(y, x) for y, x in zip(*np.nonzero(di))] == [(3, 3), (4, 4), (5, 5)]
+
+
+def _rational(v, den):
+    return int(round(v * den))
+
+
+@pytest.mark.parametrize("angle", [0.1, -0.35, 0.7, 1.2, -1.0])
+def test_rotation_general_angles_keep_pixels_and_rotate_displacements(angle):
+    """Three lossless skews move every pixel within its line, so the pixel
+    count is kept; and the composition of the shears x -= t y, y += s x,
+    x -= t y with t = tan(a/2), s = sin(a) is the rotation by a, so the
+    displacement between two single pixels turns by a.  Each skew floors
+    once: a position is off by at most 1 after the first skew, 1 + |s| after
+    the second and 2 + |t| (1 + |s|) after the third, twice that for a
+    displacement."""
+    den = 1 << 16
+    tn, sn = _rational(math.tan(angle / 2), den), _rational(math.sin(angle), den)
+    img = rnd_img(31, 40, 57, 0.3)
+    rot = osh.rotate(img, tn, sn, den)
+    assert rot.sum() == img.sum()
+    t, s = tn / den, sn / den
+    bx, by = 2 * (2 + abs(t) * (1 + abs(s))), 2 * (1 + abs(s))
+    H, W = 40, 57
+    rng = np.random.default_rng(5)
+
+    def where(y, x):
+        one = np.zeros((H, W), np.uint8)
+        one[y, x] = 1
+        r = osh.rotate(one, tn, sn, den)
+        assert r.shape == rot.shape and r.sum() == 1
+        ys, xs = np.nonzero(r)
+        return int(ys[0]), int(xs[0])
+    for _ in range(12):
+        (y0, x0), (y1, x1) = [(int(rng.integers(H)), int(rng.integers(W))) for _ in range(2)]
+        p0, p1 = where(y0, x0), where(y1, x1)
+        dx, dy = x1 - x0, y1 - y0
+        ex = math.cos(angle) * dx - math.sin(angle) * dy
+        ey = math.sin(angle) * dx + math.cos(angle) * dy
+        assert abs((p1[1] - p0[1]) - ex) <= bx and abs((p1[0] - p0[0]) - ey) <= by, \
+            (angle, (y0, x0), (y1, x1), p0, p1, ex, ey)
+
+
+def test_rotation_inverse_angle_returns_the_image():
+    """Rotating by a and then by -a undoes the rotation up to the frame: the
+    pixel count is kept and the shape comes back after cropping, for exact
+    (a = 90 degrees) skews."""
+    den = 1 << 16
+    img = np.zeros((15, 22), np.uint8)
+    img[2:6, 3:17] = 1
+    img[9:13, 18:20] = 1
+    fwd = osh.rotate(img, den, den, den)
+    back = osh.rotate(fwd, -den, -den, den)
+    np.testing.assert_array_equal(_crop(back), _crop(img))
+
+
+def test_line_op_slope_half_by_hand():
+    """A 3-pixel line at slope 1/2 (columns x move by -floor(x / 2)): the
+    digital line through (x=3, y=2) covers (2, 2), (3, 2) and (4, 3), so a
+    single pixel dilates to those three, and eroding those three keeps only
+    the centre (worked through the skew, the horizontal operation with
+    origin 1 and the skew back)."""
+    single = np.zeros((6, 8), np.uint8)
+    single[2, 3] = 1
+    di = osh.line_op("dilate", single, 3, 1, 2)
+    assert sorted((int(x), int(y)) for y, x in zip(*np.nonzero(di))) == [(2, 2), (3, 2), (4, 3)]
+    er = osh.line_op("erode", di, 3, 1, 2)
+    assert [(int(x), int(y)) for y, x in zip(*np.nonzero(er))] == [(3, 2)]
