@@ -146,8 +146,10 @@ CALIB_TAG = "BitwiseOrFunctor"
 
 
 def short_kernel_name(name):
-    """'void col_and_kernel<false>(RowsIn, int, ...)' -> 'col_and_kernel'."""
-    n = name.strip()
+    """'void morph::(anonymous namespace)::col_and_kernel<false>(RowsIn, ...)'
+    -> 'col_and_kernel'; other names lose their template arguments and
+    parameter list."""
+    n = name.strip().replace("(anonymous namespace)", "anon")
     if n.startswith("void "):
         n = n[5:]
     depth, out = 0, []
@@ -161,7 +163,7 @@ def short_kernel_name(name):
         elif depth == 0:
             out.append(ch)
     n = "".join(out).strip()
-    return n.split("::")[-1] if n.startswith("morph::") else n
+    return n.split("::")[-1] if n.startswith("morph::") else n.replace("anon::", "")
 
 
 def _csv_rows(directory, suffix):
