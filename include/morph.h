@@ -184,6 +184,22 @@ int morph_close_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_s
  */
 int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src,
                       void *ws, size_t ws_bytes, morph_stream_t stream);
+/*
+ * Allocation-free morph_pack_to_rle, for callers that cannot allocate device
+ * memory or pass a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, result and run
+ * count contract as morph_pack_to_rle, without ws: its scratch (the row
+ * counts and the scan's partial sums) is a fixed device array of 16 MiB
+ * that the library keeps on every GPU it runs on until the process ends.
+ * At most MORPH_NOALLOC_MAX_ROWS rows (npages*height) per call; more
+ * returns MORPH_E_UNSUPPORTED before anything is queued.  Every call on one
+ * GPU uses that GPU's one array: calls that overlap on a GPU (other
+ * streams, other threads) race, so the caller serialises them.  No HIP
+ * allocation, free or event creation happens in the call (its launches are
+ * not traced).
+ */
+#define MORPH_NOALLOC_MAX_ROWS 4000000
+int morph_pack_to_rle_noalloc(const morph_rle_t *dst, const morph_bitmap_t *src, morph_stream_t stream);
 /* Run-length image -> packed bitmap (pad bits 0).  src must be canonical;
  * offsets in row_ptr are clamped to src->capacity.  MORPH_E_UNSUPPORTED when
  * rows * words per row reaches 2^32. */

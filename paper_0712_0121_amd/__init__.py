@@ -31,7 +31,8 @@ __all__ = [
     "morph_version", "morph_strerror", "morph_last_hip_error", "morph_copy_async",
     "morph_erode_rect_packed", "morph_dilate_rect_packed", "morph_open_rect_packed",
     "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
-    "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_rle_to_pack",
+    "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_pack_to_rle_noalloc",
+    "MORPH_NOALLOC_MAX_ROWS", "morph_rle_to_pack",
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
     "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes", "page_desc",
     "morph_batch_launch", "Trace",
@@ -109,6 +110,7 @@ def _load():
         "morph_last_hip_error": (ctypes.c_char_p, []),
         "morph_copy_async": (ctypes.c_int, [P, P, SZ, P]),
         "morph_pack_to_rle": (ctypes.c_int, [RL, BM, P, SZ, P]),
+        "morph_pack_to_rle_noalloc": (ctypes.c_int, [RL, BM, P]),
         "morph_rle_to_pack": (ctypes.c_int, [BM, RL, P]),
         "morph_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, SE]),
         "morph_rle_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
@@ -339,6 +341,17 @@ def morph_pack_to_rle(dst: RLE, src: Bitmap, ws=None, stream=None):
     p, n = _ws(ws)
     _check(_lib.morph_pack_to_rle(ctypes.byref(d), ctypes.byref(r), p, n, _stream(stream)),
            "morph_pack_to_rle")
+
+
+MORPH_NOALLOC_MAX_ROWS = 4000000     # rows per call of morph_pack_to_rle_noalloc (include/morph.h)
+
+
+def morph_pack_to_rle_noalloc(dst: RLE, src: Bitmap, stream=None):
+    """morph_pack_to_rle with the library's fixed device scratch instead of a
+    workspace (nothing allocated); calls that overlap on one GPU race."""
+    d, r = dst.struct(), src.struct()
+    _check(_lib.morph_pack_to_rle_noalloc(ctypes.byref(d), ctypes.byref(r), _stream(stream)),
+           "morph_pack_to_rle_noalloc")
 
 
 def morph_copy_async(dst_ptr: int, src_ptr: int, nbytes: int, stream=None):

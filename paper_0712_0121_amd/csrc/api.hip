@@ -614,6 +614,21 @@ int morph_pack_to_rle(const morph_rle_t *dst, const morph_bitmap_t *src, void *w
     return MORPH_OK;
 }
 
+int morph_pack_to_rle_noalloc(const morph_rle_t *dst, const morph_bitmap_t *src, morph_stream_t stream)
+{
+    if (!rle_ok(dst) || !bitmap_ok(src)) return MORPH_E_INVAL;
+    if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
+        return MORPH_E_SHAPE;
+    const size_t ext = bitmap_extent(src);
+    if (overlap(dst->row_ptr, rle_extent_rp(dst), src->words, ext) ||
+        (dst->capacity && overlap(dst->runs, rle_extent_runs(dst), src->words, ext)))
+        return MORPH_E_ALIAS;
+    if ((long long)src->height * src->npages > MORPH_NOALLOC_MAX_ROWS) return MORPH_E_UNSUPPORTED;
+    hipError_t e = rle_from_packed_noalloc(*dst, *src, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 int morph_rle_to_pack(const morph_bitmap_t *dst, const morph_rle_t *src, morph_stream_t stream)
 {
     if (!bitmap_ok(dst) || !rle_ok(src)) return MORPH_E_INVAL;

@@ -150,7 +150,11 @@ hipError_t launch_mask(const MaskPage &p, const MaskRunsArg &m, int npages, hipS
 
 // ------------------------------------------------------------- run-length
 hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
-                           hipStream_t stream);
+                           hipStream_t stream, bool traced = true);
+// rle_from_packed with its scratch in the library's fixed device array
+// (no allocation); rows = npages * height must be at most
+// MORPH_NOALLOC_MAX_ROWS.
+hipError_t rle_from_packed_noalloc(const morph_rle_t &dst, const morph_bitmap_t &src, hipStream_t stream);
 hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipStream_t stream);
 size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t se);
 bool rle_uses_scan(morph_se_t se);   // between-line pass by block prefix scans

@@ -23,6 +23,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace morph {
 
@@ -1492,7 +1493,8 @@ static unsigned long long *trace_block(unsigned long long *tr, int kernel)
     return tr ? tr + (long long)kernel * 2 * kTraceSlots * kTraceStride : nullptr;
 }
 
-hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws, hipStream_t s)
+hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws, hipStream_t s,
+                           bool traced)
 {
     const int R = src.height * src.npages;
     const int nw = (src.width + 63) / 64;
@@ -1501,8 +1503,8 @@ hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, vo
     int *tmp = (int *)((char *)ws + r256((size_t)R * sizeof(int)));
     const long long pw = (long long)src.stride_words * src.height;
     const unsigned g = blocks_for(R, kRowWaves);
-    unsigned long long *tr = trace_counters();
-    trace_before(MORPH_K_PACK_TO_RLE, s);
+    unsigned long long *tr = traced ? trace_counters() : nullptr;
+    if (traced) trace_before(MORPH_K_PACK_TO_RLE, s);
     const bool narrow = nw <= kNarrowRowWords;
     const unsigned gg = blocks_for(R, kGroupsPerBlock);
     if (narrow)
@@ -1521,7 +1523,7 @@ hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, vo
         hipLaunchKernelGGL((pack_to_rle_kernel<true>), dim3(g), dim3(64 * kRowWaves), 0, s, src.words, nw,
                            src.stride_words, src.height, R, pw, pad, nullptr, dst.row_ptr, dst.runs,
                            (long long)dst.capacity, trace_block(tr, MORPH_K_PACK_TO_RLE));
-    trace_after(MORPH_K_PACK_TO_RLE, s, 8.0 * nw * R + 4.0 * (R + 1));
+    if (traced) trace_after(MORPH_K_PACK_TO_RLE, s, 8.0 * nw * R + 4.0 * (R + 1));
     return hipGetLastError();
 }
 
@@ -1895,6 +1897,54 @@ hipError_t shift_rows_rle(const morph_rle_t &dst, const morph_rle_t &src, const 
                        nullptr, dst.row_ptr, dst.runs, (long long)dst.capacity, trace_block(tr, MORPH_K_SHIFT_RLE));
     trace_after(MORPH_K_SHIFT_RLE, s, 8.0 * R + 4.0 * (R + 1));
     return hipGetLastError();
+}
+
+// --------------------------------------------- conversion without allocation
+// Scratch of the allocation-free conversion (row counts, then the scan's
+// block sums): a file-scope device array that every GPU the library runs on
+// holds until the process ends.  Its name is a host-side stand-in in host
+// code; the device address comes from hipGetSymbolAddress, looked up once
+// per device (with that device current) on the first call there, and only
+// that address is ever passed to kernels.  Every call on a GPU shares the
+// array: calls that overlap on one GPU race.  Nothing in it needs clearing:
+// the count launch writes every row's count and the scan every block sum.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+static hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+static_assert(((size_t)MORPH_NOALLOC_MAX_ROWS * 4 + 255) / 256 * 256 +
+                  ((size_t)MORPH_NOALLOC_MAX_ROWS + kScanBlock - 1) / kScanBlock * 4 + 4 <= kNoAllocScratchBytes,
+              "the fixed scratch must hold the counts and scan partials of MORPH_NOALLOC_MAX_ROWS rows");
+
+hipError_t rle_from_packed_noalloc(const morph_rle_t &dst, const morph_bitmap_t &src, hipStream_t s)
+{
+    const long long R = (long long)src.height * src.npages;
+    if (R > MORPH_NOALLOC_MAX_ROWS) return hipErrorInvalidValue;   // checked by the entry point first
+    void *ws = nullptr;
+    const hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return e;
+    return rle_from_packed(dst, src, ws, s, false);
 }
 
 int rle_validate(const morph_rle_t &r, hipStream_t s, hipError_t *err)

@@ -322,3 +322,19 @@ def test_rotation_rationals_closed_forms():
     t, s, _ = M.rotation_rationals(0.4, den)
     assert M.rotation_rationals(-0.4, den) == (-t, -s, den)
     assert M.rotation_rationals(np.pi / 2, 1000) == (1000, 1000, 1000)
+
+
+def test_pack_to_rle_noalloc_argument_checks():
+    """Checked on the host before the fixed scratch is looked up: bad
+    structs, shape mismatches, and more rows than the scratch holds (the
+    addresses are far apart and never dereferenced)."""
+    words, rowp, runs = 1 << 40, 2 << 40, 3 << 40
+    rows = M.MORPH_NOALLOC_MAX_ROWS + 1
+    bm = M.morph_bitmap_t(words, 64, rows, 1, 1)
+    rl = M.morph_rle_t(64, rows, 1, rowp, runs, 16)
+    f = M._lib.morph_pack_to_rle_noalloc
+    assert f(ctypes.byref(rl), ctypes.byref(bm), None) == -8          # too many rows
+    bm2 = M.morph_bitmap_t(words, 64, 10, 1, 1)
+    assert f(ctypes.byref(rl), ctypes.byref(bm2), None) == -2         # shapes differ
+    assert f(None, ctypes.byref(bm2), None) == -1
+    assert f(ctypes.byref(rl), None, None) == -1
