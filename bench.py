@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
-    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose", "components", "masks"], default="all",
+    ap.add_argument("--only", choices=["all", "packed", "rle", "transpose", "components", "masks", "serve"],
+                    default="all",
                     help="restrict the step (for profiling); the JSON value needs 'all'; 'transpose', "
-                         "'components' and 'masks' print only those measurements")
+                         "'components', 'masks' and 'serve' print only those measurements")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -74,34 +75,75 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def cpu_baseline(pool, min_seconds):
-    """The oracle as it is: every operation of the workload on whole pages,
-    packed results by brute force, run-length results as encode(brute force
-    (decode(runs))), pages taken one by one until min_seconds have passed."""
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name"), from /proc/cpuinfo."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_workload(img, method):
+    """The step's 40 operations on one page by the oracle: the 20 packed
+    results (brute force or the summed-area evaluator), the 20 run-length
+    results as encode(op(decode(runs))), and the conversions."""
     import oracle
-    pages = 0
-    px = 0
+    f = oracle.apply if method == "brute" else oracle.sat_apply
+    for _, se in LETTER_SES:
+        for op in OPS:
+            f(op, img, se)
+    rp, runs = oracle.rle_encode(img)
+    for _, se in LETTER_SES:
+        for op in OPS:
+            oracle.rle_apply(op, rp, runs, img.shape[1], img.shape[0], se, method=method)
+    last = oracle.rle_encode(f("close", img, LETTER_SES[-1][1]))
+    oracle.rle_decode(*last, img.shape[1], img.shape[0])
+    return 2 * len(LETTER_SES) * len(OPS) * img.size
+
+
+def _time_oracle(images, method, min_seconds):
+    px, n = 0, 0
     t0 = time.perf_counter()
     while True:
-        img = pool[pages % len(pool)].img
-        for _, se in LETTER_SES:
-            for op in OPS:
-                oracle.apply(op, img, se)
-        rp, runs = oracle.rle_encode(img)
-        for _, se in LETTER_SES:
-            for op in OPS:
-                oracle.rle_apply(op, rp, runs, img.shape[1], img.shape[0], se)
-        last = oracle.rle_encode(oracle.apply("close", img, LETTER_SES[-1][1]))
-        oracle.rle_decode(*last, img.shape[1], img.shape[0])
-        pages += 1
-        px += 2 * len(LETTER_SES) * len(OPS) * img.size
+        px += _oracle_workload(images[n % len(images)], method)
+        n += 1
         if time.perf_counter() - t0 >= min_seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": oracle.threads(), "kind": "oracle",
+    return px / dt / 1e9, n, dt
+
+
+def cpu_baseline(pool, min_seconds):
+    """The oracle as it is, timed on the host on bounded samples of the
+    step's workload: brute force on all threads (the reported value), brute
+    force on one thread (over bands of 128 rows of a page), and the
+    summed-area evaluator on all threads and on one, in Gpixel/s."""
+    import oracle
+    nthreads = oracle.threads()
+    v, pages, dt = _time_oracle([p.img for p in pool], "brute", min_seconds)
+    band = [p.img[:128].copy() for p in pool[:2]]
+    oracle.set_threads(1)
+    try:
+        v1, n1, dt1 = _time_oracle(band, "brute", min_seconds / 2)
+        s1, sn1, sdt1 = _time_oracle([p.img for p in pool], "sat", min_seconds / 4)
+    finally:
+        oracle.set_threads(nthreads)
+    sv, sn, sdt = _time_oracle([p.img for p in pool], "sat", min_seconds / 4)
+    return {"value": v, "unit": "Gpixel/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d letter page(s) 2550x3300 through the full workload (20 ops brute force on "
-                      "bytes + 20 ops as encode(brute(decode(runs))) + conversions), %.1f s"
-                      % (pages, dt)}
+                      "bytes + 20 ops as encode(brute(decode(runs))) + conversions), %.1f s" % (pages, dt),
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "one_thread": {"value": v1, "unit": "Gpixel/s", "cores": 1,
+                           "sample": "%d band(s) of 2550x128 through the same workload, %.1f s" % (n1, dt1)},
+            "sat": {"value": sv, "unit": "Gpixel/s", "cores": nthreads,
+                    "sample": "%d letter page(s), the same workload by the summed-area evaluator, %.1f s"
+                              % (sn, sdt)},
+            "sat_one_thread": {"value": s1, "unit": "Gpixel/s", "cores": 1,
+                               "sample": "%d letter page(s), summed-area evaluator, %.1f s" % (sn1, sdt1)}}
 
 
 def profiled_traffic(kernel):
@@ -315,10 +357,18 @@ def bench_batched(M, dev, tuner, n=256):
         tuned.append((d_, s_, it.op, it.se, tr, sw))
     plan_t = M.BatchPlan(tuned)
     t_t = time_ms(lambda: plan_t.run(use_graph=True))
+    # the representation choice per page (density counted on the device,
+    # the tuner's packed-vs-runs table), then the routed batch timed
+    routed = M.RoutedBatch(tuned, tuner=tuner)
+    t_r = time_ms(lambda: routed.run(use_graph=True))
+    dens = routed.densities
     ex = lambda ms: {"ms": ms, "gpixel_s": px / (ms / 1e3) / 1e9, "hbm_gbs": alg / (ms / 1e3) / 1e9,
                      "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
     return {"pages": n, "gpixel": px / 1e9, "alg_bytes": alg, "per_page_launches": ex(t_pp),
-            "persistent_graph": ex(t_b), "persistent_graph_tuned": ex(t_t), "tiles": plan.tiles,
+            "persistent_graph": ex(t_b), "persistent_graph_tuned": ex(t_t),
+            "routed": dict(ex(t_r), routes=routed.route_counts(),
+                           density_min=min(dens), density_max=max(dens)),
+            "tiles": plan.tiles,
             "tiles_tuned": plan_t.tiles, "tune_seconds": tune_s}
 
 
@@ -341,7 +391,7 @@ class _frozen_requests:
         gc.unfreeze()
 
 
-def bench_serving(M, dev, seconds):
+def bench_serving(M, dev, seconds, tuner=None):
     """Serving: Poisson arrivals of pages sized as in the mixed batch, each with
     the chain close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5, under a 64 GB
     HBM budget; served (continuous batching) vs plain per-page path on the
@@ -368,7 +418,7 @@ def bench_serving(M, dev, seconds):
 
     budget = 64 << 30
     runner = serve.PlainRunner(dev)
-    ex = serve.GpuExecutor(dev, recycle_outputs=True)     # results are not kept
+    ex = serve.GpuExecutor(dev, recycle_outputs=True, tuner=tuner)     # results are not kept
     # warm both paths (first launches, allocator pools), then measure
     # saturation with bursts of requests all arriving at time 0
     serve.run_trace_plain(runner, reqs(64), np.zeros(64), keep_results=False)
@@ -415,19 +465,25 @@ def bench_serving(M, dev, seconds):
             hi = mid
     p1 = lo
     points = []
-    for name, qps in (("0.5x plain saturation", 0.5 * p0), ("0.9x plain saturation", 0.9 * p0),
-                      ("0.9x served saturation", 0.9 * p1)):
+    # the fourth point holds the device to a budget of about four of the
+    # largest pages' buffer pairs, so that admission waits for memory
+    small = 4 * 2 * 6600 * 80 * 8
+    for name, qps, bud in (("0.5x plain saturation", 0.5 * p0, budget), ("0.9x plain saturation", 0.9 * p0, budget),
+                           ("0.9x served saturation", 0.9 * p1, budget),
+                           ("0.9x served saturation, %.0f MB budget" % (small / 1e6), 0.9 * p1, small)):
         arrivals = pagegen.poisson_trace(qps, seconds, seed=5001)
         served = reqs(len(arrivals))
         with _frozen_requests():
-            srv = serve.Server(ex, budget, keep_results=False)
+            srv = serve.Server(ex, bud, keep_results=False)
             serve.run_trace_served(srv, served, arrivals, timeout=seconds * 20 + 60)
-        plain = reqs(len(arrivals))
-        with _frozen_requests():
-            serve.run_trace_plain(runner, plain, arrivals, keep_results=False)
-        points.append({"load": name, "qps": qps, "requests": len(arrivals),
+        plain = None
+        if bud == budget:               # the plain path keeps one page on the device: no budget
+            plain = reqs(len(arrivals))
+            with _frozen_requests():
+                serve.run_trace_plain(runner, plain, arrivals, keep_results=False)
+        points.append({"load": name, "qps": qps, "requests": len(arrivals), "budget_gb": bud / 2**30,
                        "served": serve.latency_stats(srv.completed, 0.0),
-                       "plain": serve.latency_stats(plain, 0.0),
+                       "plain": serve.latency_stats(plain, 0.0) if plain is not None else None,
                        "served_launches": srv.launches, "served_peak_hbm_gb": srv.peak_used / 2**30})
     # device-only latency: the chain's launches on one resident page, no
     # copies and no queueing, page by page (the plain path is warm by now)
@@ -437,6 +493,7 @@ def bench_serving(M, dev, seconds):
     runner.timing = False
     dev_ms = np.array(runner.device_ms)
     return {"chain": "close 1x41 -> open 3x3 -> dilate 15x5 -> erode 15x5", "budget_gb": 64,
+            "operations_routed_to_runs": ex.rle_ops,
             "seconds_per_trace": seconds,
             "device_only_ms": {"n": int(len(dev_ms)), "p50": float(np.percentile(dev_ms, 50)),
                                "p99": float(np.percentile(dev_ms, 99)), "max": float(dev_ms.max())},
@@ -685,8 +742,9 @@ def bench_small(M, dev, reps=50):
 
 
 def bench_repr(M, dev, tuner):
-    """Bitmap vs run-length choice on 2550x3300 pages at 1%, 10%, 40% black
-    (conversions included), as the autotuner records it."""
+    """Bitmap vs run-length choice on batches of 16 2550x3300 pages at 1%,
+    10%, 40% black (conversions included), as the autotuner records it; the
+    mixed batch routes its pages by this table."""
     import pagegen
     pages = {}
     for d in (0.01, 0.10, 0.40):
@@ -717,6 +775,12 @@ def main():
     words_pool = [torch.from_numpy(p.words().view(np.int64)) for p in pool]
     host = torch.cat([words_pool[i % len(pool)] for i in range(B)], dim=0)
     src = M.Bitmap(host.to(dev), W, H, B)
+    if args.only == "serve":
+        # the serving workload alone (traces of --serve-seconds each)
+        from paper_0712_0121_amd.tune import Tuner
+        res = bench_serving(M, dev, args.serve_seconds, Tuner(device="cuda:0"))
+        print(json.dumps({"serving": res}), flush=True)
+        return
     if args.only in ("transpose", "components", "masks"):
         del host
         res = {"transpose": lambda: bench_transpose(M, dev, src, None), "components": lambda: bench_components(M, dev, src),
@@ -953,9 +1017,11 @@ def main():
         tuner = Tuner(device="cuda:0")
         # serving first: its latencies depend on the host's state (pinned
         # pools, allocator caches), which the other extras leave loaded
-        out["serving"] = bench_serving(M, dev, args.serve_seconds)
-        out["batched"] = bench_batched(M, dev, tuner)
+        # the representation table first: the batch and the serving
+        # executor route pages by it
         out["repr_choice"] = bench_repr(M, dev, tuner)
+        out["serving"] = bench_serving(M, dev, args.serve_seconds, tuner)
+        out["batched"] = bench_batched(M, dev, tuner)
         out["density_sweep"] = bench_density(M, dev)
         out["small_image"] = bench_small(M, dev)
         out["transpose"] = bench_transpose(M, dev, src, breakdown.get("rle", {}).get("ms_per_op"))

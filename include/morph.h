@@ -149,6 +149,16 @@ int morph_open_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src,
 int morph_close_rect_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, morph_se_t se,
                             void *ws, size_t ws_bytes, morph_stream_t stream);
 
+/*
+ * Black pixels of every page: counts[p] (device int64, npages entries,
+ * 8-byte aligned) = the number of 1 pixels of page p, pad bits excluded.
+ * The input of the choice between the packed and the run-length path by
+ * page density (section "Experiments", subsection "2D Rectangular Masks":
+ * the representation is picked at run time, conversion costs included).
+ * counts must not overlap the image (MORPH_E_ALIAS).
+ */
+int morph_popcount_pages(const morph_bitmap_t *src, int64_t *counts, morph_stream_t stream);
+
 /* ---- run-length images -------------------------------------------------- */
 /*
  * The same four operations on run-length images (section "2D Morphological

@@ -57,6 +57,7 @@ def _load():
         lib.oracle_rle_encode.argtypes = [P, P, P, I, I]
         lib.oracle_rle_decode.argtypes = [P, P, P, I, I]
         lib.oracle_threads.restype = I
+        lib.oracle_set_threads.argtypes = [I]
         _lib = lib
     return _lib
 
@@ -64,6 +65,11 @@ def _load():
 def threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the OpenMP loops from now on (timing on one thread)."""
+    _load().oracle_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

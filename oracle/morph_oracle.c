@@ -44,6 +44,16 @@ int oracle_threads(void)
 #endif
 }
 
+/* Sets that number (n >= 1), for timing the oracle on one thread. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 #define PIX(img, W, x, y) ((img)[(size_t)(y) * (size_t)(W) + (size_t)(x)])
 
 /* Erosion by brute force: out(x,y) = 1 iff every pixel of the window

@@ -34,8 +34,9 @@ __all__ = [
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_pack_to_rle_noalloc",
     "MORPH_NOALLOC_MAX_ROWS", "morph_rle_to_pack",
     "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
-    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "morph_batch_workspace_bytes", "page_desc",
+    "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "RoutedBatch", "RleRoute", "morph_batch_workspace_bytes", "page_desc",
     "morph_batch_launch", "Trace",
+    "morph_popcount_pages", "page_densities",
     "morph_transpose_packed", "morph_transpose_rle", "morph_transpose_rle_workspace_bytes",
     "morph_rect_rlet", "morph_rlet_workspace_bytes",
     "morph_rle_label", "morph_rle_label_workspace_bytes", "morph_rle_component_stats", "morph_component_t",
@@ -127,6 +128,7 @@ def _load():
         "morph_trace_end": (ctypes.c_int, [ctypes.POINTER(morph_kernel_trace_t), P]),
         "morph_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
         "morph_transpose_packed": (ctypes.c_int, [BM, BM, P]),
+        "morph_popcount_pages": (ctypes.c_int, [BM, P, P]),
         "morph_transpose_rle": (ctypes.c_int, [RL, RL, P, SZ, P]),
         "morph_transpose_rle_workspace_bytes": (SZ, [I32, I32, I32]),
         "morph_rect_rlet": (ctypes.c_int, [ctypes.c_int, RL, RL, SE, P, SZ, P]),
@@ -395,6 +397,34 @@ def morph_transpose_packed(dst: Bitmap, src: Bitmap, stream=None):
            "morph_transpose_packed")
 
 
+def morph_popcount_pages(src: Bitmap, counts: torch.Tensor, stream=None):
+    """counts (device int64, npages entries) = black pixels of every page."""
+    r = src.struct()
+    _check(_lib.morph_popcount_pages(ctypes.byref(r), ctypes.c_void_p(counts.data_ptr()), _stream(stream)),
+           "morph_popcount_pages")
+
+
+def page_densities(bitmaps, stream=None):
+    """Black fraction of every page of the given bitmaps (in order, stacked
+    pages each), counted on the device; one synchronisation to read them."""
+    bitmaps = list(bitmaps)
+    if not bitmaps:
+        return []
+    n = sum(b.npages for b in bitmaps)
+    counts = torch.empty(n, dtype=torch.int64, device=bitmaps[0].words.device)
+    k = 0
+    for b in bitmaps:
+        morph_popcount_pages(b, counts[k:k + b.npages], stream)
+        k += b.npages
+    c = counts.tolist()
+    out, k = [], 0
+    for b in bitmaps:
+        for _ in range(b.npages):
+            out.append(c[k] / float(b.width * b.height))
+            k += 1
+    return out
+
+
 def morph_transpose_rle_workspace_bytes(width, height, npages=1) -> int:
     return int(_lib.morph_transpose_rle_workspace_bytes(int(width), int(height), int(npages)))
 
@@ -549,6 +579,110 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class RleRoute:
+    """Pages sent down the run-length path one at a time: bitmap -> runs ->
+    operation -> bitmap (the paper's runtime choice counts the conversions
+    as part of that path).  The run-length images and workspaces are shared
+    by every page and grow to the largest page seen; the pages run one after
+    another on a stream, so one set serves them all."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.W = self.H = 0
+        self.rp = self.runs = self.rp2 = self.runs2 = None
+        self.ws_p2r = self.ws_op = None
+        self.ws_op_bytes = 0
+
+    def _fit(self, W, H, op, s, stream):
+        cap = morph_rle_max_runs(W, H)
+        with torch.cuda.stream(stream) if isinstance(stream, torch.cuda.Stream) else _nullctx():
+            if self.rp is None or self.rp.numel() < H + 1 or self.runs.shape[0] < cap:
+                rows = max(H, self.H) + 1
+                n = max(cap, self.runs.shape[0] if self.runs is not None else 0)
+                self.rp = torch.empty(rows, dtype=torch.int32, device=self.device)
+                self.rp2 = torch.empty(rows, dtype=torch.int32, device=self.device)
+                self.runs = torch.empty((n, 2), dtype=torch.int32, device=self.device)
+                self.runs2 = torch.empty((n, 2), dtype=torch.int32, device=self.device)
+                self.H = max(H, self.H)
+            need = morph_pack_to_rle_workspace_bytes(W, H)
+            if self.ws_p2r is None or self.ws_p2r.numel() < need:
+                self.ws_p2r = torch.empty(need, dtype=torch.uint8, device=self.device)
+            need = morph_rle_workspace_bytes(op, W, H, 1, s)
+            if need > self.ws_op_bytes:
+                self.ws_op = torch.empty(need, dtype=torch.uint8, device=self.device)
+                self.ws_op_bytes = need
+
+    def run(self, dst: Bitmap, src: Bitmap, op, s, stream=None):
+        if src.npages != 1 or dst.npages != 1:
+            raise ValueError("RleRoute runs single pages")
+        W, H = src.width, src.height
+        self._fit(W, H, op, s, stream)
+        r_in = RLE(self.rp[:H + 1], self.runs, W, H)
+        r_out = RLE(self.rp2[:H + 1], self.runs2, W, H)
+        morph_pack_to_rle(r_in, src, self.ws_p2r, stream)
+        RLE_OPS[op](r_out, r_in, s, self.ws_op, stream)
+        morph_rle_to_pack(dst, r_out, stream)
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+class RoutedBatch:
+    """A batch whose pages each go down the packed or the run-length path, as
+    the tuner chooses from the page's black density, its operation and its
+    element size (section "Experiments", subsection "2D Rectangular Masks":
+    the representation is picked at run time, conversion costs included).
+    The packed pages run as one persistent launch (BatchPlan); each
+    run-length page as bitmap -> runs -> operation -> bitmap (RleRoute).
+
+    items: (dst, src, op, se[, tile_rows, strip_words]) with single-page
+    bitmaps.  routes: a list of 'packed' / 'rle' to force the choice;
+    otherwise tuner.choose_repr(density, op, se) picks it (every page
+    'packed' without a tuner), the densities counted on the device by
+    morph_popcount_pages unless given."""
+
+    def __init__(self, items, tuner=None, routes=None, densities=None, stream=None):
+        items = list(items)
+        if routes is None:
+            if tuner is None:
+                routes = ["packed"] * len(items)
+            else:
+                if densities is None:
+                    densities = page_densities([it[1] for it in items], stream)
+                routes = [tuner.choose_repr(d, it[2], tuple(it[3])) for d, it in zip(densities, items)]
+        routes = list(routes)
+        if len(routes) != len(items) or any(r not in ("packed", "rle") for r in routes):
+            raise ValueError("one route, 'packed' or 'rle', per page")
+        self.routes = routes
+        self.densities = densities
+        pk = [it for it, r in zip(items, routes) if r == "packed"]
+        self.rle_items = [tuple(it[:4]) for it, r in zip(items, routes) if r == "rle"]
+        self.plan = BatchPlan(pk, stream) if pk else None
+        self.rle = RleRoute(self.rle_items[0][1].words.device) if self.rle_items else None
+
+    @property
+    def tiles(self) -> int:
+        return self.plan.tiles if self.plan is not None else 0
+
+    def route_counts(self):
+        return {"packed": self.routes.count("packed"), "rle": self.routes.count("rle")}
+
+    def run(self, use_graph: bool = True, stream=None):
+        if self.plan is not None:
+            self.plan.run(use_graph, stream)
+        for dst, src, op, s in self.rle_items:
+            self.rle.run(dst, src, op, s, stream)
+
+    def close(self):
+        if self.plan is not None:
+            self.plan.close()
 
 
 def _descs(items):

@@ -753,6 +753,15 @@ int morph_transpose_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src,
     return MORPH_OK;
 }
 
+int morph_popcount_pages(const morph_bitmap_t *src, int64_t *counts, morph_stream_t stream)
+{
+    if (!bitmap_ok(src) || !counts || (((uintptr_t)counts) & 7)) return MORPH_E_INVAL;
+    if (overlap(counts, (size_t)src->npages * 8, src->words, bitmap_extent(src))) return MORPH_E_ALIAS;
+    hipError_t e = popcount_pages(*src, (unsigned long long *)counts, (hipStream_t)stream);
+    if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+    return MORPH_OK;
+}
+
 size_t morph_transpose_rle_workspace_bytes(int32_t width, int32_t height, int32_t npages)
 {
     if (width < 1 || height < 1 || npages < 1 || (long long)width * npages > 0x7fffffffLL) return 0;

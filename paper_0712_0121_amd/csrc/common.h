@@ -120,6 +120,9 @@ hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev
 hipError_t launch_reset_counter(int *queue_dev, hipStream_t stream);
 int device_cu_count();
 
+// counts[p] = black pixels of page p (pad bits excluded).
+hipError_t popcount_pages(const morph_bitmap_t &src, unsigned long long *counts, hipStream_t stream);
+
 // Transpose of every page of a packed bitmap (dst: width = src height,
 // height = src width).
 hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream);

@@ -716,6 +716,44 @@ __global__ __launch_bounds__(256) void shift_rows_kernel(const uint64_t *__restr
     dst[r * dstride + j] = o;
 }
 
+
+// ------------------------------------------------------------ pixel counts
+// Black pixels per page, the input of the choice between the packed and the
+// run-length path: counts[page] is cleared by block 0 of the first launch,
+// then every workgroup adds the popcount of a range of rows of one page
+// (pad bits masked off) with one 64-bit atomic.
+__global__ void clear_counts_kernel(unsigned long long *counts, int n)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) counts[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void popcount_kernel(const uint64_t *__restrict__ src, int nw, int stride, int H,
+                                                      long long page_words, uint64_t padmask, int rows_per_block,
+                                                      int blocks_per_page, unsigned long long *counts)
+{
+    __shared__ unsigned long long part[4];
+    const int page = (int)(blockIdx.x / (unsigned)blocks_per_page);
+    const int blk = (int)(blockIdx.x - (unsigned)page * (unsigned)blocks_per_page);
+    const int y0 = blk * rows_per_block, y1 = min(H, y0 + rows_per_block);
+    const uint64_t *p = src + (long long)page * page_words;
+    unsigned long long c = 0;
+    const long long n = (long long)(y1 - y0) * nw;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        const int y = y0 + (int)(i / nw), j = (int)(i - (long long)(y - y0) * nw);
+        uint64_t v = p[(long long)y * stride + j];
+        if (j == nw - 1) v &= padmask;
+        c += (unsigned long long)__popcll(v);
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(counts + page, t);
+    }
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -940,6 +978,22 @@ hipError_t shift_rows_packed(const morph_bitmap_t &dst, const morph_bitmap_t &sr
                        src.width, nws, src.stride_words, dst.words, dst.width, nwd, dst.stride_words, shifts, fill,
                        total);
     trace_after(MORPH_K_SHIFT, stream, 8.0 * R * ((double)nws + nwd) + 4.0 * R);
+    return hipGetLastError();
+}
+
+hipError_t popcount_pages(const morph_bitmap_t &src, unsigned long long *counts, hipStream_t stream)
+{
+    const int P = src.npages, H = src.height, nw = (src.width + 63) / 64;
+    const uint64_t pad = (src.width % 64) ? ((1ull << (src.width % 64)) - 1) : ~0ull;
+    hipLaunchKernelGGL(clear_counts_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, counts, P);
+    // about 1024 workgroups over the stack, at least 8 rows each
+    const int per_page = std::max(1, std::min((H + 7) / 8, (1024 + P - 1) / P));
+    const int rows = (H + per_page - 1) / per_page;
+    const int bpp = (H + rows - 1) / rows;
+    const long long blocks = (long long)bpp * P;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(popcount_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, src.words, nw,
+                       src.stride_words, H, (long long)src.stride_words * H, pad, rows, bpp, counts);
     return hipGetLastError();
 }
 

@@ -235,10 +235,18 @@ class GpuExecutor:
     downloads_in_order = True
 
     def __init__(self, device="cuda:0", ws_bytes=64 << 20, staging_slots=4, direct_max=2,
-                 recycle_outputs=False):
+                 recycle_outputs=False, tuner=None):
         import torch
         import paper_0712_0121_amd as M
         self.M, self.torch = M, torch
+        # representation choice per operation (section "Experiments",
+        # runtime selection with conversion costs): with a tuner, an
+        # operation whose (density, op, element) entry says 'rle' runs as
+        # bitmap -> runs -> operation -> bitmap instead of in the batch
+        self.tuner = tuner
+        self._rle_possible = {}
+        self.rle = None
+        self.rle_ops = 0
         self.device = torch.device(device)
         self.compute = torch.cuda.Stream(device=self.device)
         self.copy = torch.cuda.Stream(device=self.device)        # uploads
@@ -315,18 +323,62 @@ class GpuExecutor:
             bufs = (a, b)
             descs = [M.page_desc(bufs[(k + 1) % 2], bufs[k % 2], op, se) for k, (op, se) in enumerate(r.chain)]
             cache[key] = descs
-        r.state = {"cur": a, "nxt": b, "pair": (a, b, cache), "up": ev, "host": host, "descs": descs}
+        r.state = {"cur": a, "nxt": b, "pair": (a, b, cache), "up": ev, "host": host, "descs": descs,
+                   "routes": self._routes(r, host)}
+
+    def _routes(self, r: Request, host):
+        """The path of each operation of the chain, or None when every one is
+        packed.  The page's black density is counted on the host copy, and
+        only for chains the tuner could send to runs."""
+        if self.tuner is None:
+            return None
+        key = tuple(r.chain)
+        poss = self._rle_possible.get(key)
+        if poss is None:
+            poss = any(self.tuner.rle_possible(op, se) for op, se in r.chain)
+            self._rle_possible[key] = poss
+        if not poss:
+            return None
+        nw = (r.W + 63) // 64
+        words = host.numpy().view(np.uint64)[:, :nw] if hasattr(host, "numpy") else np.asarray(host)[:, :nw]
+        black = int(np.bitwise_count(words[:, :nw - 1]).sum())
+        tail = (1 << (r.W - 64 * (nw - 1))) - 1 if r.W % 64 else (1 << 64) - 1
+        black += int(np.bitwise_count(words[:, nw - 1] & np.uint64(tail)).sum())
+        density = black / float(r.W * r.H)
+        routes = [self.tuner.choose_repr(density, op, se) for op, se in r.chain]
+        return routes if "rle" in routes else None
 
     def launch(self, reqs):
         torch, M = self.torch, self.M
-        items = []
+        items, packed, rle = [], [], []
         for r in reqs:
             st = r.state
             if st.get("up") is not None:
                 self.compute.wait_event(st["up"])
                 self.ev_pool.append(st["up"])
                 st["up"] = None
-            items.append(st["descs"][r.pos])
+            rt = st.get("routes")
+            if rt is not None and rt[r.pos] == "rle":
+                rle.append(r)
+            else:
+                items.append(st["descs"][r.pos])
+                packed.append(r)
+        if rle:
+            # run-length operations go one page at a time on the compute
+            # stream, ahead of the batched launch of the packed ones
+            if self.rle is None:
+                self.rle = M.RleRoute(self.device)
+            for r in rle:
+                op, se = r.chain[r.pos]
+                self.rle.run(r.state["nxt"], r.state["cur"], op, se, self.compute)
+            self.rle_ops += len(rle)
+            reqs = packed
+        if not items:
+            ev = self._event()
+            ev.record(self.compute)
+            for r in rle:
+                r.state["ev"] = ev
+            return ev
         if len(items) <= self.direct_max:
             with torch.cuda.stream(self.compute):
                 for r in reqs:
@@ -334,7 +386,7 @@ class GpuExecutor:
                     M.PACKED[op](r.state["nxt"], r.state["cur"], se, self.ws)
                 ev = self._event()
                 ev.record(self.compute)
-            for r in reqs:
+            for r in reqs + rle:
                 r.state["ev"] = ev
             return ev
         k = self.slot
@@ -345,7 +397,7 @@ class GpuExecutor:
         ev = self._event()
         ev.record(self.compute)
         self.staging_ev[k] = ev
-        for r in reqs:
+        for r in reqs + rle:
             r.state["ev"] = ev
         return ev
 

@@ -10,9 +10,10 @@ choice, measured on the device and cached as JSON.
 * Representation.  The paper picks between bit-blit and run-length code at
   run time from the mask size and resolution, or from the output complexity
   (section "Experiments", runtime selection including conversion costs).
-  Here the tuner times, on pages of a given black density, the packed
-  operation against bitmap -> runs -> operation -> bitmap, and records the
-  faster one per (density bucket, operation, element size class).
+  Here the tuner times, on batches of pages of a given black density, the
+  packed operation against bitmap -> runs -> operation -> bitmap, and
+  records the faster one per (density bucket, operation, element size
+  class); RoutedBatch and the serving executor route each page by it.
 
 The cache key includes the device name; MORPH_TUNE_CACHE overrides the path.
 """
@@ -29,6 +30,10 @@ H_BUCKETS = (1, 8, 24, 48, 96)             # element heights up to each bound
 STRIDE_BUCKETS = (24, 48, 96, 1 << 30)     # words per row up to each bound
 DENSITY_BUCKETS = (0.03, 0.2, 1.0)         # black density up to each bound
 SIZE_CLASSES = (5, 16, 64, 1 << 30)        # max(w, h) up to each bound
+# the elements timed for each size class (the largest class is left to the
+# packed path: no entry, so choose_repr answers 'packed')
+REPR_SES = (((3, 3, 1, 1),), ((9, 9, 4, 4), (15, 5, 7, 2)),
+            ((41, 1, 20, 0), (1, 41, 0, 20), (31, 31, 15, 15)))
 
 
 def bucket(v, bounds):
@@ -152,34 +157,58 @@ class Tuner:
                         print("shape", key, best, "%.3f ms" % best_t)
         return self.table["shape"]
 
-    def tune_repr(self, pages_by_density, ops=("erode", "dilate"), ses=((41, 1, 20, 0), (1, 41, 0, 20), (3, 3, 1, 1)),
-                  verbose=False):
-        """pages_by_density: {density: (W, H, host words)}."""
+    def tune_repr(self, pages_by_density, ops=("erode", "dilate", "open", "close"), ses_by_class=None,
+                  batch=16, verbose=False):
+        """pages_by_density: {density: (W, H, host words)}.  For every density,
+        operation and element size class, times the representative elements
+        of the class on a batch of `batch` stacked copies of the page (a
+        batch, not one page that would stay in cache) along both paths: the
+        packed operation, and bitmap -> runs -> operation -> bitmap.  The
+        path with the smaller summed time wins the (density bucket,
+        operation, size class) entry."""
         import torch
         import paper_0712_0121_amd as M
+        if ses_by_class is None:
+            ses_by_class = REPR_SES
         dev = torch.device(self.device)
         for dens, (W, H, words) in pages_by_density.items():
-            src = M.Bitmap.from_words(words, W, device=dev)
-            dst = M.Bitmap.empty(W, H, device=dev)
-            r_in = M.RLE.empty(W, H, device=dev)
-            r_out = M.RLE.empty(W, H, device=dev)
-            back = M.Bitmap.empty(W, H, device=dev)
-            w_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
+            host = np.concatenate([words] * batch)
+            src = M.Bitmap.from_words(host, W, npages=batch, device=dev)
+            del host
+            dst = M.Bitmap.empty(W, H, batch, device=dev)
+            back = M.Bitmap.empty(W, H, batch, device=dev)
+            r_in = M.RLE.empty(W, H, batch, device=dev)
+            r_out = M.RLE.empty(W, H, batch, device=dev)
+            w_p2r = torch.empty(M.morph_pack_to_rle_workspace_bytes(W, H * batch), dtype=torch.uint8, device=dev)
             for op in ops:
-                for se in ses:
-                    w_rle = torch.empty(M.morph_rle_workspace_bytes(op, W, H, 1, se), dtype=torch.uint8, device=dev)
-                    n_pk = M.morph_workspace_bytes(op, 0, W, H, se)
-                    w_pk = torch.empty(n_pk, dtype=torch.uint8, device=dev) if n_pk else None
-                    t_pk = self._time(lambda: M.PACKED[op](dst, src, se, w_pk))
+                for ses in ses_by_class:
+                    t_pk = t_rle = 0.0
+                    for se in ses:
+                        w_rle = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, batch, se), 1),
+                                            dtype=torch.uint8, device=dev)
+                        n_pk = M.morph_workspace_bytes(op, 0, W, H * batch, se)
+                        w_pk = torch.empty(n_pk, dtype=torch.uint8, device=dev) if n_pk else None
+                        t_pk += self._time(lambda: M.PACKED[op](dst, src, se, w_pk), 3)
 
-                    def rle_path():
-                        M.morph_pack_to_rle(r_in, src, w_p2r)
-                        M.RLE_OPS[op](r_out, r_in, se, w_rle)
-                        M.morph_rle_to_pack(back, r_out)
-                    t_rle = self._time(rle_path)
-                    key = repr_key(dens, op, se)
+                        def rle_path():
+                            M.morph_pack_to_rle(r_in, src, w_p2r)
+                            M.RLE_OPS[op](r_out, r_in, se, w_rle)
+                            M.morph_rle_to_pack(back, r_out)
+                        t_rle += self._time(rle_path, 3)
+                        del w_rle, w_pk
+                    key = repr_key(dens, op, ses[0])
                     self.table["repr"][key] = {"best": "packed" if t_pk <= t_rle else "rle",
-                                               "packed_ms": t_pk, "rle_ms": t_rle}
+                                               "packed_ms": t_pk, "rle_ms": t_rle, "pages": batch,
+                                               "elements": [list(se) for se in ses]}
                     if verbose:
                         print("repr", key, self.table["repr"][key])
+            del src, dst, back, r_in, r_out, w_p2r
+            torch.cuda.empty_cache()
         return self.table["repr"]
+
+    def rle_possible(self, op, se):
+        """Whether any density bucket sends (op, element size class) to runs:
+        callers skip measuring a page's density when none does."""
+        k = bucket(max(se[0], se[1]), SIZE_CLASSES)
+        suffix = "_%s_k%d" % (op, k)
+        return any(key.endswith(suffix) and v.get("best") == "rle" for key, v in self.table["repr"].items())

@@ -169,6 +169,16 @@ def test_batch_plan_argument_errors():
     assert M._lib.morph_batch_run(None, 1, None) == -1
 
 
+def test_popcount_argument_errors():
+    a, b = HostBuf(1 << 16), HostBuf(1 << 16)
+    pc = lambda s, c: M._lib.morph_popcount_pages(ctypes.byref(s), c, None)
+    assert pc(bitmap(a, 100, 10), None) == -1
+    assert pc(bitmap(a, 100, 10), b.ptr + 4) == -1               # counts not 8-byte aligned
+    assert pc(bitmap(a, 0, 10), b.ptr) == -1
+    assert pc(bitmap(a, 100, 10, stride=1), b.ptr) == -1
+    assert pc(bitmap(a, 100, 10, npages=2), a.ptr + 8) == -3      # counts inside the image
+
+
 def test_transpose_argument_errors():
     a, b = HostBuf(1 << 18), HostBuf(1 << 18)
     W, H = 100, 30

@@ -138,3 +138,62 @@ def test_full_mixed_batch_as_timed(tmp_path):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(single.to_numpy(), got, err_msg="per-page launch, page %d" % k)
     assert sizes == set(pagegen.PAGE_SIZES)
+
+
+class _ForcedTuner:
+    """A tuner whose table sends the given (density bucket, op, size class)
+    keys to runs; everything else stays packed (Tuner's own lookups)."""
+
+    def __new__(cls, tmp_path, rle_keys):
+        from paper_0712_0121_amd.tune import Tuner
+        t = Tuner(cache_path=str(tmp_path / "forced.json"))
+        t.table = {"shape": {}, "repr": {k: {"best": "rle"} for k in rle_keys}}
+        return t
+
+
+def test_routed_batch_forced_routes_match_oracle_and_packed():
+    """Pages sent down the run-length path (bitmap -> runs -> operation ->
+    bitmap) give the same bits as the packed path and the oracle: every
+    other page routed to runs, with uneven sizes, strides and elements."""
+    items = make_batch(16, 5, max_se=40)
+    srcs, dsts = upload(items)
+    _, dsts_pk = upload(items)
+    routes = ["rle" if k % 2 else "packed" for k in range(len(items))]
+    rb = M.RoutedBatch([(d, s, op, se) for d, s, (img, op, se) in zip(dsts, srcs, items)], routes=routes)
+    assert rb.route_counts() == {"packed": 8, "rle": 8}
+    plan = M.BatchPlan([(d, s, op, se) for d, s, (img, op, se) in zip(dsts_pk, srcs, items)])
+    for rep in range(2):
+        for d in dsts:
+            d.words.fill_(-1)
+        rb.run(use_graph=rep > 0)
+        plan.run(use_graph=False)
+        torch.cuda.synchronize()
+        for k, ((img, op, se), d, dp) in enumerate(zip(items, dsts, dsts_pk)):
+            got = d.to_numpy()
+            np.testing.assert_array_equal(got, dp.to_numpy(), err_msg="page %d (%s) vs packed" % (k, routes[k]))
+            np.testing.assert_array_equal(got, oracle.pack(oracle.sat_apply(op, img, se)),
+                                          err_msg="page %d %s %s %s" % (k, routes[k], op, se))
+
+
+def test_routed_batch_tuner_routes_by_density(tmp_path):
+    """The tuner's choice routes by the density the library counts on the
+    device: sparse pages (1 % black) of an operation the table sends to runs
+    take the run-length path, dense ones (40 %) stay packed, and both match
+    the oracle."""
+    from paper_0712_0121_amd.tune import repr_key
+    se = (9, 1, 4, 0)
+    tuner = _ForcedTuner(tmp_path, [repr_key(0.01, "dilate", se)])
+    items = []
+    for k, d in enumerate((0.01, 0.40, 0.01, 0.40)):
+        img = pagegen.density_page(d, 4100 + k).img[:400, :700].copy()
+        items.append((img, "dilate", se))
+    srcs, dsts = upload(items)
+    dens = M.page_densities(srcs)
+    for (img, _, _), got in zip(items, dens):
+        assert abs(got - img.mean()) < 1e-12
+    rb = M.RoutedBatch([(d, s, op, se_) for d, s, (img, op, se_) in zip(dsts, srcs, items)], tuner=tuner)
+    assert rb.routes == ["rle", "packed", "rle", "packed"]
+    rb.run()
+    torch.cuda.synchronize()
+    for (img, op, se_), d in zip(items, dsts):
+        np.testing.assert_array_equal(d.to_numpy(), oracle.pack(oracle.apply(op, img, se_)))

@@ -119,3 +119,33 @@ def test_pooled_buffers_across_traces():
         for r in reqs:
             np.testing.assert_array_equal(ex.got[r.rid], expected(r), err_msg="trace %d request %d" % (trace, r.rid))
         assert sum(len(v) for v in ex.buf_pool.values()) >= 1
+
+
+def test_served_with_run_length_routes(tmp_path):
+    """Serving with a tuner that sends the chain's opening 3x3 and erosion
+    15x5 on sparse pages (black density up to 3 %) to the run-length path:
+    those operations of the sparse requests run as bitmap -> runs ->
+    operation -> bitmap between the batched launches, and every result still
+    equals the oracle and the all-packed server's."""
+    from paper_0712_0121_amd.serve import GpuExecutor, Request, SERVE_CHAIN, chain_ses
+    from paper_0712_0121_amd.tune import Tuner, repr_key
+    chain = chain_ses(SERVE_CHAIN)
+    tuner = Tuner(cache_path=str(tmp_path / "forced.json"))
+    tuner.table = {"shape": {}, "repr": {repr_key(0.01, op, se): {"best": "rle"}
+                                         for op, se in chain if op in ("open", "erode")}}
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(12):
+        W, H = [(640, 97), (300, 211), (1275, 1650)][i % 3]
+        p = 0.01 if i % 2 else 0.3
+        img = (rng.random((H, W)) < p).astype(np.uint8)
+        words = torch.from_numpy(oracle.pack(img).view(np.int64)).pin_memory()
+        reqs.append(Request(i, W, H, words, chain))
+    arrivals = np.cumsum(rng.exponential(0.0004, len(reqs)))
+    ex = GpuExecutor(tuner=tuner)
+    s = served(reqs, arrivals, ex=ex)
+    assert ex.rle_ops == 2 * 6                    # two operations of each of the six sparse requests
+    plain = served(clone(reqs), arrivals)
+    for r, q in zip(sorted(s.completed, key=lambda r: r.rid), sorted(plain.completed, key=lambda r: r.rid)):
+        np.testing.assert_array_equal(r.result, q.result, err_msg="request %d routed vs packed" % r.rid)
+        np.testing.assert_array_equal(r.result, expected(r), err_msg="request %d vs oracle" % r.rid)

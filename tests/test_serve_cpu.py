@@ -150,3 +150,20 @@ def test_chain_is_the_serving_workload():
     assert [op for op, _ in SERVE_CHAIN] == ["close", "open", "dilate", "erode"]
     assert chain_ses(SERVE_CHAIN)[0] == ("close", (41, 1, 20, 0))
     assert chain_ses(SERVE_CHAIN)[2] == ("dilate", (5, 15, 2, 7))
+
+
+def test_tuner_rle_possible_and_choice(tmp_path):
+    """The representation lookups: a (density bucket, op, size class) entry
+    marked 'rle' routes only pages of that bucket, operation and class to
+    runs, and rle_possible sees it for any density."""
+    from paper_0712_0121_amd.tune import Tuner, repr_key
+    t = Tuner(cache_path=str(tmp_path / "t.json"))
+    t.table = {"shape": {}, "repr": {repr_key(0.01, "dilate", (9, 1, 4, 0)): {"best": "rle"},
+                                     repr_key(0.3, "erode", (3, 3, 1, 1)): {"best": "packed"}}}
+    assert t.choose_repr(0.02, "dilate", (15, 5, 7, 2)) == "rle"       # same bucket and class
+    assert t.choose_repr(0.05, "dilate", (15, 5, 7, 2)) == "packed"    # denser bucket
+    assert t.choose_repr(0.02, "dilate", (41, 1, 20, 0)) == "packed"   # larger class
+    assert t.choose_repr(0.02, "erode", (9, 1, 4, 0)) == "packed"      # other operation
+    assert t.rle_possible("dilate", (3, 11, 1, 5))
+    assert not t.rle_possible("erode", (3, 3, 1, 1))
+    assert not t.rle_possible("dilate", (3, 3, 1, 1))
