@@ -464,6 +464,7 @@ def bench_serving(M, dev, seconds, tuner=None):
         else:
             hi = mid
     p1 = lo
+    print("serving: saturation plain %.0f, served %.0f pages/s" % (p0, p1), file=sys.stderr, flush=True)
     points = []
     # the fourth point holds the device to a budget of about four of the
     # largest pages' buffer pairs, so that admission waits for memory
@@ -481,6 +482,7 @@ def bench_serving(M, dev, seconds, tuner=None):
             plain = reqs(len(arrivals))
             with _frozen_requests():
                 serve.run_trace_plain(runner, plain, arrivals, keep_results=False)
+        print("serving: %s, %d requests done" % (name, len(arrivals)), file=sys.stderr, flush=True)
         points.append({"load": name, "qps": qps, "requests": len(arrivals), "budget_gb": bud / 2**30,
                        "served": serve.latency_stats(srv.completed, 0.0),
                        "plain": serve.latency_stats(plain, 0.0) if plain is not None else None,

@@ -168,13 +168,30 @@ int morph_popcount_pages(const morph_bitmap_t *src, int64_t *counts, morph_strea
  * or union (dilation) of the run lists of h consecutive rows, computed by
  * logarithmic decomposition into pairwise merges, sections "Between Line
  * Boolean Operations" and "Efficient Binary Decompositions").
- * dst->capacity must be at least morph_rle_max_runs(width, height*npages)
- * (MORPH_E_CAPACITY otherwise).  ws: at least morph_rle_workspace_bytes(op,
- * width, height, npages, se) bytes.  Images whose worst case,
- * npages*height*ceil(width/2) runs, or whose npages*(height+h-1) extended
- * rows (twice that for elements of 9 or more rows and 2 or more columns,
- * whose between-line pass may keep two rows per extended row), reach 2^31
- * give MORPH_E_UNSUPPORTED.
+ * Any dst->capacity is accepted: the result's true run count is written to
+ * dst->row_ptr[npages*height] and runs past capacity are not written (the
+ * caller compares after the stream has passed the call and retries with a
+ * larger array; morph_rle_max_runs() never overflows).  The result must have
+ * fewer than 2^31 runs.  ws: at least morph_rle_workspace_bytes(op, width,
+ * height, npages, se) bytes.
+ *
+ * Two forms, picked by the workspace given.  The slot form (the fast one)
+ * keeps every intermediate row in a workspace slot of ceil(width/2) runs:
+ * morph_rle_workspace_bytes() gives its size, about 20 KB per image row at
+ * letter width.  It needs the worst case, npages*height*ceil(width/2)
+ * runs, and the npages*(height+h-1) extended rows (twice that for elements
+ * of 9 or more rows and 2 or more columns) below 2^31.  The band form keeps
+ * one band of rows per workgroup with every intermediate row in LDS: a
+ * count launch, a scan of the counts into row_ptr, an emit launch; its
+ * workspace, morph_rle_workspace_bytes_compact(), is about 12 bytes per row
+ * plus a fixed scratch for rows too dense for LDS.  It takes images
+ * narrower than 65536 pixels whose element needs at most 383 rows of halo
+ * (h - 1, twice that for opening and closing), any number of pages, and
+ * runs several times slower.  A workspace of at least the slot size runs
+ * the slot form; a smaller one of at least the compact size, 256-byte
+ * aligned, the band form (also when the image is too large for the slot
+ * form, where morph_rle_workspace_bytes() returns the compact size).
+ * Neither possible: MORPH_E_UNSUPPORTED.
  */
 int morph_erode_rect_rle(const morph_rle_t *dst, const morph_rle_t *src, morph_se_t se,
                          void *ws, size_t ws_bytes, morph_stream_t stream);
@@ -353,13 +370,97 @@ int morph_shift_rows_rle(const morph_rle_t *dst, const morph_rle_t *src, const i
                          void *ws, size_t ws_bytes, morph_stream_t stream);
 size_t morph_shift_rows_rle_workspace_bytes(int32_t rows);
 
+/* ---- skews, rotation, lines at a slope (sections "Scaling, Skewing, and
+ *      Rotation", "Morphology with Lines at Arbitrary Orientations") -------- */
+/*
+ * Compositions of the calls above; the integer shift of every line is
+ * computed on the device from the arguments, and the intermediate images
+ * live in the workspace (256-byte aligned, at least the bytes the matching
+ * *_workspace_bytes function returns; 0 from it means the arguments are
+ * invalid or too large).  Run-length destinations need capacity >=
+ * morph_rle_max_runs(dst width, dst height * npages).  repr is MORPH_PACKED
+ * or MORPH_RLE.
+ *
+ * Lossless skew.  axis 0 (along the lines): line y of each page moves right
+ * by floor(num (y - origin) / den) less the smallest such shift, into a
+ * destination wider by morph_skew_spread(height, num, den, origin) pixels
+ * (same height).  axis 1 (across the lines): column x moves down by
+ * floor(num (x - origin) / den) less the smallest, into a destination taller
+ * by morph_skew_spread(width, num, den, origin) (same width); it runs as
+ * transpose, skew along the lines, transpose.  Pixels that no source pixel
+ * lands on get fill (0 or 1).  den > 0.
+ */
+int64_t morph_skew_spread(int32_t lines, int32_t num, int32_t den, int32_t origin);
+size_t morph_skew_workspace_bytes(int repr, int axis, int32_t width, int32_t height, int32_t npages, int32_t num,
+                                  int32_t den, int32_t origin);
+int morph_skew_packed(int axis, const morph_bitmap_t *dst, const morph_bitmap_t *src, int32_t num, int32_t den,
+                      int32_t origin, int32_t fill, void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_skew_rle(int axis, const morph_rle_t *dst, const morph_rle_t *src, int32_t num, int32_t den,
+                   int32_t origin, int32_t fill, void *ws, size_t ws_bytes, morph_stream_t stream);
+/*
+ * Rotation by `angle` radians (|angle| <= pi/2, else MORPH_E_UNSUPPORTED) as
+ * three lossless skews about the frame centre: along the lines by
+ * -tan(angle/2), across them by sin(angle), along them by -tan(angle/2),
+ * each slope the nearest rational over 2^16 (morph_rotation_rationals with
+ * den = 65536 gives the numerators).  Every pixel is kept: the destination
+ * is morph_rotate_dims() large; new pixels are 0.
+ */
+int morph_rotation_rationals(double angle, int32_t den, int32_t *tan_num, int32_t *sin_num);
+int morph_rotate_dims(int32_t width, int32_t height, double angle, int32_t *out_width, int32_t *out_height);
+size_t morph_rotate_workspace_bytes(int repr, int32_t width, int32_t height, int32_t npages, double angle);
+int morph_rotate_packed(const morph_bitmap_t *dst, const morph_bitmap_t *src, double angle, void *ws,
+                        size_t ws_bytes, morph_stream_t stream);
+int morph_rotate_rle(const morph_rle_t *dst, const morph_rle_t *src, double angle, void *ws, size_t ws_bytes,
+                     morph_stream_t stream);
+/*
+ * Erosion (op MORPH_ERODE) or dilation (MORPH_DILATE) by a centred line of
+ * `length` pixels along the slope num/den, |num| <= den (steeper lines:
+ * transpose first): the columns are skewed so that the line lies along the
+ * rows (column x by -floor(num x / den); pixels brought in from outside
+ * take the border value, 1 for erosion and 0 for dilation), the rows get
+ * the length x 1 operation, and the inverse skew returns the original
+ * frame.  dst has src's size.
+ */
+size_t morph_line_op_workspace_bytes(int repr, int op, int32_t width, int32_t height, int32_t npages,
+                                     int32_t length, int32_t num, int32_t den);
+int morph_line_op_packed(int op, const morph_bitmap_t *dst, const morph_bitmap_t *src, int32_t length, int32_t num,
+                         int32_t den, void *ws, size_t ws_bytes, morph_stream_t stream);
+int morph_line_op_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, int32_t length, int32_t num,
+                      int32_t den, void *ws, size_t ws_bytes, morph_stream_t stream);
+
+/*
+ * Layout analysis on runs (sections "Connected Component Extraction and
+ * Statistics" and "Experiments", the layout use): spacing[0] (host) = the
+ * percentile num/den (0 < num <= den <= 2^20) of the horizontal white runs
+ * lying between two black runs of a row, over every page; spacing[1] the
+ * same for the vertical ones (found by transposing); every page dilated by
+ * the centred (spacing[0] + 1) x (spacing[1] + 1) rectangle into `smeared`
+ * (same size as src, capacity as for morph_dilate_rect_rle); the connected
+ * components of `smeared` (labels, max_runs, comp_ptr as in
+ * morph_rle_label, connectivity 4 or 8) and their statistics stats[c] for
+ * c < max_components (as morph_rle_component_stats).  Synchronous: the call
+ * waits for the stream once, after the spacings, because they set the
+ * dilation's element; the rest is queued.  A vertical spacing of 383 or
+ * more (a smear too tall for the band form of the dilation) returns
+ * MORPH_E_UNSUPPORTED after that wait.  ws: 256-byte aligned,
+ * morph_layout_rle_workspace_bytes(width, height, npages, max_runs) bytes.
+ */
+size_t morph_layout_rle_workspace_bytes(int32_t width, int32_t height, int32_t npages, int64_t max_runs);
+int morph_layout_rle(const morph_rle_t *src, int32_t num, int32_t den, int32_t connectivity,
+                     const morph_rle_t *smeared, int32_t *labels, int64_t max_runs, int32_t *comp_ptr,
+                     morph_component_t *stats, int64_t max_components, int32_t *spacing, void *ws,
+                     size_t ws_bytes, morph_stream_t stream);
+
 /* ---- sizes and checks --------------------------------------------------- */
 /* Workspace bytes an operation on one page needs (op: MORPH_ERODE ..
  * MORPH_CLOSE; repr: MORPH_PACKED or MORPH_RLE).  For a packed stack pass
  * height*npages; for a run-length stack use morph_rle_workspace_bytes. */
 size_t morph_workspace_bytes(int op, int repr, int32_t width, int32_t height, morph_se_t se);
-/* Workspace bytes of a run-length operation on npages stacked pages. */
+/* Workspace bytes of a run-length operation on npages stacked pages: the
+ * slot form's, or the band form's where the slot form cannot take the
+ * image.  _compact: the band form's (0 where it does not apply). */
 size_t morph_rle_workspace_bytes(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se);
+size_t morph_rle_workspace_bytes_compact(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se);
 /* Workspace bytes morph_pack_to_rle needs (height counts all stacked pages). */
 size_t morph_pack_to_rle_workspace_bytes(int32_t width, int32_t height);
 /* Most runs an image of this size can have: height * ceil(width/2). */
@@ -448,7 +549,10 @@ enum {
     MORPH_K_SHIFT = 14,        /* packed line shifts */
     MORPH_K_SHIFT_RLE = 15,    /* line shifts on runs (count and emit launches) */
     MORPH_K_COL_SCAN = 16,     /* between-line block prefix scans on runs (tall elements) */
-    MORPH_K_COUNT = 17
+    MORPH_K_RLE_BAND = 17,     /* run-length rectangle operation, one band per workgroup in LDS:
+                                  the launch that writes the runs */
+    MORPH_K_RLE_BAND_COUNT = 18, /* the same, the launch that counts each output row's runs */
+    MORPH_K_COUNT = 19
 };
 typedef struct {
     int64_t launches;

@@ -33,7 +33,8 @@ __all__ = [
     "morph_close_rect_packed", "morph_erode_rect_rle", "morph_dilate_rect_rle",
     "morph_open_rect_rle", "morph_close_rect_rle", "morph_pack_to_rle", "morph_pack_to_rle_noalloc",
     "MORPH_NOALLOC_MAX_ROWS", "morph_rle_to_pack",
-    "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_pack_to_rle_workspace_bytes",
+    "morph_workspace_bytes", "morph_rle_workspace_bytes", "morph_rle_workspace_bytes_compact",
+    "morph_pack_to_rle_workspace_bytes",
     "morph_rle_max_runs", "morph_rle_validate", "BatchPlan", "RoutedBatch", "RleRoute", "morph_batch_workspace_bytes", "page_desc",
     "morph_batch_launch", "Trace",
     "morph_popcount_pages", "page_densities",
@@ -90,7 +91,7 @@ class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 17
+MORPH_K_COUNT = 19
 
 
 class morph_page_desc_t(ctypes.Structure):
@@ -115,6 +116,7 @@ def _load():
         "morph_rle_to_pack": (ctypes.c_int, [BM, RL, P]),
         "morph_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, SE]),
         "morph_rle_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
+        "morph_rle_workspace_bytes_compact": (SZ, [ctypes.c_int, I32, I32, I32, SE]),
         "morph_pack_to_rle_workspace_bytes": (SZ, [I32, I32]),
         "morph_rle_max_runs": (I64, [I32, I32]),
         "morph_rle_validate": (ctypes.c_int, [RL, P]),
@@ -146,6 +148,21 @@ def _load():
         "morph_shift_rows_packed": (ctypes.c_int, [BM, BM, P, I32, P]),
         "morph_shift_rows_rle": (ctypes.c_int, [RL, RL, P, I32, P, SZ, P]),
         "morph_shift_rows_rle_workspace_bytes": (SZ, [I32]),
+        "morph_skew_spread": (I64, [I32, I32, I32, I32]),
+        "morph_skew_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, I32, I32, I32, I32]),
+        "morph_skew_packed": (ctypes.c_int, [ctypes.c_int, BM, BM, I32, I32, I32, I32, P, SZ, P]),
+        "morph_skew_rle": (ctypes.c_int, [ctypes.c_int, RL, RL, I32, I32, I32, I32, P, SZ, P]),
+        "morph_rotation_rationals": (ctypes.c_int, [ctypes.c_double, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "morph_rotate_dims": (ctypes.c_int, [I32, I32, ctypes.c_double, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "morph_rotate_workspace_bytes": (SZ, [ctypes.c_int, I32, I32, I32, ctypes.c_double]),
+        "morph_rotate_packed": (ctypes.c_int, [BM, BM, ctypes.c_double, P, SZ, P]),
+        "morph_rotate_rle": (ctypes.c_int, [RL, RL, ctypes.c_double, P, SZ, P]),
+        "morph_line_op_workspace_bytes": (SZ, [ctypes.c_int, ctypes.c_int, I32, I32, I32, I32, I32, I32]),
+        "morph_line_op_packed": (ctypes.c_int, [ctypes.c_int, BM, BM, I32, I32, I32, P, SZ, P]),
+        "morph_line_op_rle": (ctypes.c_int, [ctypes.c_int, RL, RL, I32, I32, I32, P, SZ, P]),
+        "morph_layout_rle_workspace_bytes": (SZ, [I32, I32, I32, I64]),
+        "morph_layout_rle": (ctypes.c_int, [RL, I32, I32, I32, RL, P, I64, P, P, I64, ctypes.POINTER(I32), P, SZ,
+                                             P]),
     }
     for op in OPS:
         sig["morph_%s_rect_packed" % op] = (ctypes.c_int, [BM, BM, SE, P, SZ, P])
@@ -769,11 +786,31 @@ def rect_packed(op: str, src: Bitmap, s, dst: Bitmap | None = None, stream=None)
     return dst
 
 
-def rect_rle(op: str, src: RLE, s, dst: RLE | None = None, stream=None) -> RLE:
-    if dst is None:
-        dst = RLE.empty(src.width, src.height, src.npages, device=src.row_ptr.device)
-    ws = _alloc_ws(morph_rle_workspace_bytes(op, src.width, src.height, src.npages, s), src.row_ptr.device)
+def morph_rle_workspace_bytes_compact(op, width, height, npages, s) -> int:
+    op = OPS.index(op) if isinstance(op, str) else int(op)
+    return int(_lib.morph_rle_workspace_bytes_compact(op, int(width), int(height), int(npages), _se(s)))
+
+
+def rect_rle(op: str, src: RLE, s, dst: RLE | None = None, stream=None, compact: bool = False) -> RLE:
+    """op in OPS on a run-length image; allocates dst and workspace with torch
+    (compact: the band form's small workspace instead of the slot form's).
+    Without dst the result array starts at twice the input's runs plus one
+    per row (the input count is read back: a synchronisation) and, if the
+    result has more runs than that, is sized from the reported total and the
+    operation runs again."""
+    size = morph_rle_workspace_bytes_compact if compact else morph_rle_workspace_bytes
+    ws = _alloc_ws(size(op, src.width, src.height, src.npages, s), src.row_ptr.device)
+    if dst is not None:
+        RLE_OPS[op](dst, src, s, ws, stream)
+        return dst
+    rows = src.height * src.npages
+    cap = min(2 * src.nruns() + rows + 16, morph_rle_max_runs(src.width, rows))
+    dst = RLE.empty(src.width, src.height, src.npages, capacity=cap, device=src.row_ptr.device)
     RLE_OPS[op](dst, src, s, ws, stream)
+    total = dst.nruns()
+    if total > cap:
+        dst = RLE.empty(src.width, src.height, src.npages, capacity=total, device=src.row_ptr.device)
+        RLE_OPS[op](dst, src, s, ws, stream)
     return dst
 
 
@@ -856,23 +893,36 @@ def histogram_percentile(hist, num: int, den: int, stream=None):
 
 
 def layout_boxes(src: RLE, num: int = 1, den: int = 3, connectivity: int = 8, stream=None):
-    """Layout analysis on runs: gx, gy = percentile num/den of the horizontal
-    and vertical (by transposition) white runs between black ones over the
+    """Layout analysis on runs (morph_layout_rle): gx, gy = percentile num/den
+    of the horizontal and vertical white runs between black ones over the
     whole stack; the pages dilated by the centred (gx + 1) x (gy + 1)
     rectangle; the connected components of the result and their boxes.
-    Returns (gx, gy, boxes, sums, comp_ptr); the element is read back to
-    the host (a synchronisation) because it sets the launch."""
-    _, hw = run_histograms(src, stream)
-    t = transpose_rle(src, stream)
-    _, vw = run_histograms(t, stream)
-    g = torch.cat([histogram_percentile(hw, num, den, stream), histogram_percentile(vw, num, den, stream)])
-    gx, gy = (int(v) for v in g.tolist())
-    del t
-    s = (gx + 1, gy + 1, (gx + 1) // 2, (gy + 1) // 2)
-    smeared = rect_rle("dilate", src, s, stream=stream)
-    labels, comp_ptr = label_components(smeared, connectivity, stream)
-    boxes, sums = component_stats(smeared, labels, comp_ptr, stream)
-    return gx, gy, boxes, sums, comp_ptr
+    Returns (gx, gy, boxes, sums, comp_ptr).  The library waits for the
+    stream once, to read the spacings; the label array starts at twice the
+    input's runs plus one per row and is enlarged once if the smeared image
+    has more runs."""
+    dev = src.row_ptr.device
+    smeared = RLE.empty(src.width, src.height, src.npages, device=dev)
+    comp_ptr = torch.empty(src.npages + 1, dtype=torch.int32, device=dev)
+    spacing = (ctypes.c_int32 * 2)()
+    max_runs = min(2 * src.nruns() + src.height * src.npages, 2 ** 31 - 2)
+    for attempt in range(2):
+        labels = torch.empty(max(max_runs, 1), dtype=torch.int32, device=dev)
+        stats = torch.empty((max(max_runs, 1), 10), dtype=torch.int32, device=dev)
+        ws = _alloc_ws(_lib.morph_layout_rle_workspace_bytes(src.width, src.height, src.npages, max_runs), dev)
+        p, nb = _ws(ws)
+        _check(_lib.morph_layout_rle(ctypes.byref(src.struct()), num, den, connectivity, ctypes.byref(smeared.struct()),
+                                     ctypes.c_void_p(labels.data_ptr()), max_runs,
+                                     ctypes.c_void_p(comp_ptr.data_ptr()), ctypes.c_void_p(stats.data_ptr()),
+                                     max_runs, spacing, p, nb, _stream(stream)), "morph_layout_rle")
+        total = int(comp_ptr[-1].item())
+        if total >= 0:
+            break
+        max_runs = smeared.nruns()              # the labels ran out of room: once more, sized exactly
+    if total < 0:
+        raise MorphError(-6, "layout_boxes: labelling ran out of room")
+    raw = stats[:total]
+    return spacing[0], spacing[1], raw[:, :4], raw[:, 4:].contiguous().view(torch.int64), comp_ptr
 
 
 def mask_packed(op: str, src: Bitmap, mask: Mask, dst: Bitmap | None = None, stream=None) -> Bitmap:
@@ -918,65 +968,91 @@ def _transpose(img, stream=None):
     return transpose_packed(img, stream) if isinstance(img, Bitmap) else transpose_rle(img, stream)
 
 
-def skew_rows(src, num: int, den: int, origin: int, fill: int = 0, stream=None):
-    """Lossless skew along the lines: line y moves by floor(num (y - origin) /
-    den), less the smallest such shift; the frame widens by their spread.
-    Returns (image, shifts as a numpy array)."""
-    import numpy as np
+def _empty_like_repr(img, width, height):
+    if isinstance(img, Bitmap):
+        return Bitmap.empty(width, height, img.npages, device=img.words.device)
+    return RLE.empty(width, height, img.npages, device=img.row_ptr.device)
+
+
+def _skew(axis, src, num, den, origin, fill, stream):
     if den <= 0:
         raise ValueError("den must be positive")
-    v = (num * (np.arange(src.height, dtype=np.int64) - origin)) // den
-    v = v - v.min()
-    shifts = torch.from_numpy(np.tile(v, src.npages).astype(np.int32)).to(_dev(src))
-    return shift_rows(src, shifts, src.width + int(v.max()), fill, stream), v
+    repr_ = MORPH_PACKED if isinstance(src, Bitmap) else MORPH_RLE
+    lines = src.height if axis == 0 else src.width
+    spread = int(_lib.morph_skew_spread(lines, num, den, origin))
+    W, H = (src.width + spread, src.height) if axis == 0 else (src.width, src.height + spread)
+    dst = _empty_like_repr(src, W, H)
+    n = _lib.morph_skew_workspace_bytes(repr_, axis, src.width, src.height, src.npages, num, den, origin)
+    if n == 0:
+        raise MorphError(-8, "morph_skew: sizes out of range")
+    ws = torch.empty(n, dtype=torch.uint8, device=_dev(src))
+    p, nb = _ws(ws)
+    f = _lib.morph_skew_packed if repr_ == MORPH_PACKED else _lib.morph_skew_rle
+    _check(f(axis, ctypes.byref(dst.struct()), ctypes.byref(src.struct()), num, den, origin, fill, p, nb,
+             _stream(stream)), "morph_skew")
+    # along the lines the workspace starts with the library's shift table:
+    # the shifts of the lines of the first page
+    v = ws[: 4 * lines].view(torch.int32).cpu().numpy().astype("int64") if axis == 0 else None
+    return dst, v
+
+
+def skew_rows(src, num: int, den: int, origin: int, fill: int = 0, stream=None):
+    """Lossless skew along the lines (morph_skew_packed / morph_skew_rle, axis
+    0): line y moves by floor(num (y - origin) / den), less the smallest such
+    shift; the frame widens by their spread.  Returns (image, the shifts of
+    the lines of one page, read back from the library's table)."""
+    return _skew(0, src, num, den, origin, fill, stream)
 
 
 def skew_cols(src, num: int, den: int, origin: int, fill: int = 0, stream=None):
-    """Lossless skew across the lines (column x moves down by floor(num (x -
-    origin) / den) less the smallest): transpose, skew the lines, transpose."""
-    t, v = skew_rows(_transpose(src, stream), num, den, origin, fill, stream)
-    return _transpose(t, stream), v
+    """Lossless skew across the lines (axis 1: column x moves down by
+    floor(num (x - origin) / den) less the smallest).  Returns (image, None)."""
+    return _skew(1, src, num, den, origin, fill, stream)
 
 
 def rotation_rationals(angle: float, den: int = 1 << 16):
-    """(tan_num, sin_num, den): tan(angle / 2) and sin(angle) as rationals."""
-    import math
-    return int(round(math.tan(angle / 2) * den)), int(round(math.sin(angle) * den)), den
+    """(tan_num, sin_num, den): tan(angle / 2) and sin(angle) as the nearest
+    rationals over den (morph_rotation_rationals)."""
+    t, sn = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.morph_rotation_rationals(float(angle), int(den), ctypes.byref(t), ctypes.byref(sn)),
+           "morph_rotation_rationals")
+    return t.value, sn.value, den
 
 
-def rotate(src, tan_num: int, sin_num: int, den: int, stream=None):
-    """Rotation by three lossless skews about the frame centre (along the
-    lines by -tan(a/2), across them by sin(a), along them by -tan(a/2)); the
-    frame grows to hold every pixel."""
-    a, _ = skew_rows(src, -tan_num, den, src.height // 2, 0, stream)
-    a, _ = skew_cols(a, sin_num, den, a.width // 2, 0, stream)
-    a, _ = skew_rows(a, -tan_num, den, a.height // 2, 0, stream)
-    return a
+def rotate(src, angle: float, stream=None):
+    """Rotation by angle radians (|angle| <= pi/2) as three lossless skews
+    about the frame centre (morph_rotate_packed / morph_rotate_rle); the frame
+    grows to hold every pixel."""
+    ow, oh = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.morph_rotate_dims(src.width, src.height, float(angle), ctypes.byref(ow), ctypes.byref(oh)),
+           "morph_rotate_dims")
+    repr_ = MORPH_PACKED if isinstance(src, Bitmap) else MORPH_RLE
+    dst = _empty_like_repr(src, ow.value, oh.value)
+    n = _lib.morph_rotate_workspace_bytes(repr_, src.width, src.height, src.npages, float(angle))
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=_dev(src))
+    p, nb = _ws(ws)
+    f = _lib.morph_rotate_packed if repr_ == MORPH_PACKED else _lib.morph_rotate_rle
+    _check(f(ctypes.byref(dst.struct()), ctypes.byref(src.struct()), float(angle), p, nb, _stream(stream)),
+           "morph_rotate")
+    return dst
 
 
 def line_op(op: str, src, length: int, num: int, den: int, stream=None):
     """Erosion or dilation by a centred line of `length` pixels along the
-    slope num/den (|num| <= den): the columns skewed so that the line becomes
-    horizontal (pixels brought in from outside take the border value: 1 for
-    erosion, 0 for dilation), the horizontal operation, and the inverse skew
-    into the original frame."""
-    import numpy as np
+    slope num/den, |num| <= den (morph_line_op_packed / morph_line_op_rle)."""
     if op not in ("erode", "dilate"):
         raise ValueError("line_op: erode or dilate")
-    if abs(num) > den:
+    if den <= 0 or abs(num) > den:
         raise ValueError("line_op: |slope| must be at most 1 (transpose for steeper lines)")
-    dev = _dev(src)
-    fill = 1 if op == "erode" else 0
-    W, H, P = src.width, src.height, src.npages
-    v = np.array([-((num * x) // den) for x in range(W)], dtype=np.int64)
-    off = -int(v.min())
-    Ht = H + int(v.max()) + off
-    fwd = torch.from_numpy(np.tile(v + off, P).astype(np.int32)).to(dev)
-    back = torch.from_numpy(np.tile(-(v + off), P).astype(np.int32)).to(dev)
-    t = _transpose(src, stream)                            # W lines of length H per page
-    sk = shift_rows(t, fwd, Ht, fill, stream)
-    flat = _transpose(sk, stream)                          # Ht x W: the line is horizontal
-    se_ = (length, 1, length // 2, 0)
-    res = rect_packed(op, flat, se_, stream=stream) if isinstance(flat, Bitmap) else rect_rle(op, flat, se_, stream=stream)
-    t2 = _transpose(res, stream)
-    return _transpose(shift_rows(t2, back, H, 0, stream), stream)
+    repr_ = MORPH_PACKED if isinstance(src, Bitmap) else MORPH_RLE
+    k = OPS.index(op)
+    dst = _empty_like_repr(src, src.width, src.height)
+    n = _lib.morph_line_op_workspace_bytes(repr_, k, src.width, src.height, src.npages, length, num, den)
+    if n == 0:
+        raise MorphError(-8, "morph_line_op: sizes out of range")
+    ws = torch.empty(n, dtype=torch.uint8, device=_dev(src))
+    p, nb = _ws(ws)
+    f = _lib.morph_line_op_packed if repr_ == MORPH_PACKED else _lib.morph_line_op_rle
+    _check(f(k, ctypes.byref(dst.struct()), ctypes.byref(src.struct()), length, num, den, p, nb, _stream(stream)),
+           "morph_line_op")
+    return dst

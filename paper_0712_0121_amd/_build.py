@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmorph.so")
-SOURCES = ("api.hip", "packed.hip", "rle.hip", "components.hip")
+SOURCES = ("api.hip", "packed.hip", "rle.hip", "components.hip", "compose.hip", "rle_band.hip")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -545,16 +545,28 @@ static int rect_rle(int op, const morph_rle_t *dst, const morph_rle_t *src, morp
     if (dst->width != src->width || dst->height != src->height || dst->npages != src->npages)
         return MORPH_E_SHAPE;
     if (rle_alias(dst, src)) return MORPH_E_ALIAS;
-    // slot rows are indexed in 32 bits (their runs in 64); the result's row
-    // offsets are int32
-    const long long ext = (long long)src->npages * (src->height + (long long)se.h - 1) * (rle_uses_scan(se) ? 2 : 1);
-    if (ext >= 0x7fffffffLL ||
-        (long long)src->npages * src->height * (((long long)src->width + 1) / 2) >= 0x7fffffffLL)
-        return MORPH_E_UNSUPPORTED;
-    if (dst->capacity < morph_rle_max_runs(dst->width, dst->height * dst->npages)) return MORPH_E_CAPACITY;
-    const size_t need = rle_op_workspace(op, src->width, src->height * src->npages, src->height, se);
-    if (!ws || ws_bytes < need) return MORPH_E_WORKSPACE;
-    hipError_t e = rle_rect_op(op, *dst, *src, se, ws, ws_bytes, stream);
+    // Two forms.  The slot form (the fast one) keeps every intermediate row
+    // in a workspace slot sized for the worst case and indexes slot rows in
+    // 32 bits.  The band form keeps the intermediates in LDS and needs only
+    // the row counts; it runs when the workspace given is too small for the
+    // slot form, or the image too large for it, and the band form takes
+    // the element and width.
+    const long long ext =
+        (long long)src->npages * (src->height + (long long)se.h - 1) * (rle_uses_scan(se) ? 2 : 1);
+    const bool slot_ok = ext < 0x7fffffffLL &&
+                         (long long)src->npages * src->height * (((long long)src->width + 1) / 2) < 0x7fffffffLL;
+    const size_t need = slot_ok ? rle_op_workspace(op, src->width, src->height * src->npages, src->height, se) : 0;
+    const bool band_ok = rle_band_applies(op, src->width, se);
+    const size_t need_band = band_ok ? rle_band_workspace(op, src->width, (long long)src->height * src->npages, se) : 0;
+    hipError_t e;
+    if (slot_ok && ws && ws_bytes >= need) {
+        e = rle_rect_op(op, *dst, *src, se, ws, ws_bytes, stream);
+    } else if (band_ok && ws && ws_bytes >= need_band && !(((uintptr_t)ws) & 255)) {
+        e = rle_band_op(op, *dst, *src, se, ws, stream);
+    } else {
+        if (!slot_ok && !band_ok) return MORPH_E_UNSUPPORTED;
+        return MORPH_E_WORKSPACE;
+    }
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
     return MORPH_OK;
 }
@@ -588,7 +600,18 @@ size_t morph_rle_workspace_bytes(int op, int32_t width, int32_t height, int32_t 
 {
     if (width < 1 || height < 1 || npages < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE)
         return 0;
+    const long long ext = (long long)npages * (height + (long long)se.h - 1) * (rle_uses_scan(se) ? 2 : 1);
+    if (ext >= 0x7fffffffLL || (long long)npages * height * (((long long)width + 1) / 2) >= 0x7fffffffLL)
+        return morph_rle_workspace_bytes_compact(op, width, height, npages, se);
     return rle_op_workspace(op, width, height * npages, height, se);
+}
+
+size_t morph_rle_workspace_bytes_compact(int op, int32_t width, int32_t height, int32_t npages, morph_se_t se)
+{
+    if (width < 1 || height < 1 || npages < 1 || !se_ok(se) || op < MORPH_ERODE || op > MORPH_CLOSE)
+        return 0;
+    if (!rle_band_applies(op, width, se) || (long long)height * npages >= 0x7fffffffLL) return 0;
+    return rle_band_workspace(op, width, (long long)height * npages, se);
 }
 
 size_t morph_pack_to_rle_workspace_bytes(int32_t width, int32_t height)
@@ -1144,7 +1167,7 @@ const char *morph_kernel_name(int k)
                                                "decode_transpose_kernel", "components",
                                                "component_stats_kernel", "run_hist_kernel", "mask_kernel",
                                                "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel",
-                                               "col_scan_kernel"};
+                                               "col_scan_kernel", "rle_band_kernel", "rle_band_count_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

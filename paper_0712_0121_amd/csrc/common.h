@@ -160,6 +160,12 @@ hipError_t rle_from_packed(const morph_rle_t &dst, const morph_bitmap_t &src, vo
 hipError_t rle_from_packed_noalloc(const morph_rle_t &dst, const morph_bitmap_t &src, hipStream_t stream);
 hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipStream_t stream);
 size_t rle_op_workspace(int op, int32_t W, int32_t rows, int32_t H, morph_se_t se);
+// The band form of the rectangle operations on runs (every intermediate in
+// LDS): whether it takes (op, width, element), its workspace, the launch.
+bool rle_band_applies(int op, int32_t W, morph_se_t se);
+size_t rle_band_workspace(int op, int32_t W, long long rows, morph_se_t se);
+hipError_t rle_band_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se, void *ws,
+                       hipStream_t stream);
 bool rle_uses_scan(morph_se_t se);   // between-line pass by block prefix scans
 hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, morph_se_t se,
                        void *ws, size_t ws_bytes, hipStream_t stream);

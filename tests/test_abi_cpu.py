@@ -129,10 +129,20 @@ def test_rle_argument_errors(op):
     assert call(rle(a, W, H, cap), rle(b, W, H, cap), M.morph_se_t(5, 5, 5, 2)) == -1
     assert call(rle(a, W, H, cap), rle(b, W + 1, H, cap)) == -2
     assert call(rle(a, W, H, cap), rle(a, W, H, cap)) == -3
-    assert call(rle(a, W, H, cap - 1), rle(b, W, H, cap)) == -6
+    # any output capacity is accepted: the true run count lands in row_ptr
+    # and runs past capacity are not written (here the workspace check is next)
+    assert call(rle(a, W, H, 1), rle(b, W, H, cap)) == -4
     assert call(rle(a, W, H, cap), rle(b, W, H, cap)) == -4
     need = M.morph_rle_workspace_bytes(op, W, H, 1, (5, 5, 2, 2))
-    assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, HostBuf(16).ptr, need - 1) == -4
+    small = M.morph_rle_workspace_bytes_compact(op, W, H, 1, (5, 5, 2, 2))
+    assert need > 0 and small > 0
+    # below the slot form's size and misaligned for the band form, or below both
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, HostBuf(16).ptr | 1, need - 1) == -4
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), se, 1 << 40, min(need, small) - 1) == -4
+    # letter pages: the band form's workspace is a small fraction of the slot form's
+    big = (51, 51, 25, 25)
+    assert M.morph_rle_workspace_bytes_compact(op, 2550, 3300, 256, big) * 50 < \
+        M.morph_rle_workspace_bytes(op, 2550, 3300, 256, big)
     assert call(rle(a, W, H, -1), rle(b, W, H, cap)) == -1
     assert call(rle(a, W, H, cap), rle(b, W, H, cap, runs_off=4 * (H + 1) + 64)) == -1   # runs not 8-byte aligned (188)
     # addresses 1 TiB apart, never dereferenced: the size check comes first
@@ -348,3 +358,77 @@ def test_pack_to_rle_noalloc_argument_checks():
     assert f(ctypes.byref(rl), ctypes.byref(bm2), None) == -2         # shapes differ
     assert f(None, ctypes.byref(bm2), None) == -1
     assert f(ctypes.byref(rl), None, None) == -1
+
+
+def test_composition_argument_errors():
+    """Skews, rotation and line operations reject bad arguments on the host."""
+    a, b, w = HostBuf(1 << 20), HostBuf(1 << 20), HostBuf(1 << 22)
+    ws = (w.ptr + 255) & ~255
+    L = M._lib
+    W, H = 100, 30
+    sp = L.morph_skew_spread(H, 1, 3, 0)
+    assert sp == (H - 1) // 3
+    assert L.morph_skew_spread(H, -1, 3, 0) == -((-(H - 1)) // 3)          # floor, not truncation
+    assert L.morph_skew_spread(H, 7, 2, 11) == (7 * (H - 1 - 11)) // 2 - (7 * -11) // 2
+    assert L.morph_skew_spread(H, 1, 0, 0) == -1
+    assert L.morph_skew_spread(0, 1, 3, 0) == -1
+    n = L.morph_skew_workspace_bytes(0, 0, W, H, 1, 1, 3, 0)
+    assert n >= H * 4
+    assert L.morph_skew_workspace_bytes(0, 2, W, H, 1, 1, 3, 0) == 0
+    assert L.morph_skew_workspace_bytes(0, 0, W, H, 1, 1, 0, 0) == 0
+    assert L.morph_skew_workspace_bytes(1, 1, W, H, 1, 1, 3, 0) > L.morph_skew_workspace_bytes(0, 1, W, H, 1, 1, 3, 0)
+    sk = lambda axis, d, s_, num=1, den=3, fill=0, p=ws, nb=n: L.morph_skew_packed(
+        axis, ctypes.byref(d), ctypes.byref(s_), num, den, 0, fill, p, nb, None)
+    assert sk(0, bitmap(a, W + sp, H), bitmap(b, W, H), den=0) == -1
+    assert sk(0, bitmap(a, W + sp, H), bitmap(b, W, H), fill=2) == -1
+    assert sk(2, bitmap(a, W + sp, H), bitmap(b, W, H)) == -1
+    assert sk(0, bitmap(a, W, H), bitmap(b, W, H)) == -2                  # frame not widened
+    assert sk(0, bitmap(a, W + sp, H), bitmap(b, W, H), nb=n - 1) == -4
+    assert sk(0, bitmap(a, W + sp, H), bitmap(b, W, H), p=ws + 8) == -4    # not 256-byte aligned
+    assert sk(1, bitmap(a, W, H), bitmap(b, W, H)) == -2                  # frame not heightened
+    t, s_ = ctypes.c_int32(), ctypes.c_int32()
+    assert L.morph_rotation_rationals(0.5, 0, ctypes.byref(t), ctypes.byref(s_)) == -1
+    assert L.morph_rotation_rationals(2.0, 1000, ctypes.byref(t), ctypes.byref(s_)) == -8
+    assert L.morph_rotation_rationals(float("nan"), 1000, ctypes.byref(t), ctypes.byref(s_)) == -8
+    ow, oh = ctypes.c_int32(), ctypes.c_int32()
+    assert L.morph_rotate_dims(W, H, 0.0, ctypes.byref(ow), ctypes.byref(oh)) == 0
+    assert (ow.value, oh.value) == (W, H)
+    assert L.morph_rotate_dims(W, H, 1.5707963267948966, ctypes.byref(ow), ctypes.byref(oh)) == 0
+    assert oh.value >= W and ow.value >= H                                # a quarter turn swaps the sides
+    assert L.morph_rotate_dims(W, H, 3.0, ctypes.byref(ow), ctypes.byref(oh)) == -8
+    assert L.morph_rotate_workspace_bytes(0, W, H, 1, 3.0) == 0
+    rn = L.morph_rotate_workspace_bytes(0, W, H, 1, 0.5)
+    L.morph_rotate_dims(W, H, 0.5, ctypes.byref(ow), ctypes.byref(oh))
+    rot = lambda d, s_, ang=0.5, nb=rn: L.morph_rotate_packed(ctypes.byref(d), ctypes.byref(s_), ang, ws, nb, None)
+    assert rot(bitmap(a, W, H), bitmap(b, W, H)) == -2
+    assert rot(bitmap(a, ow.value, oh.value), bitmap(b, W, H), ang=3.0) == -8
+    assert rot(bitmap(a, ow.value, oh.value), bitmap(b, W, H), nb=rn - 1) == -4
+    ln = L.morph_line_op_workspace_bytes(0, 0, W, H, 1, 9, 1, 2)
+    assert ln > 0
+    assert L.morph_line_op_workspace_bytes(0, 2, W, H, 1, 9, 1, 2) == 0    # open: not a line operation
+    assert L.morph_line_op_workspace_bytes(0, 0, W, H, 1, 9, 3, 2) == 0    # |slope| > 1
+    lo = lambda op, d, s_, length=9, num=1, den=2, nb=ln: L.morph_line_op_packed(
+        op, ctypes.byref(d), ctypes.byref(s_), length, num, den, ws, nb, None)
+    assert lo(2, bitmap(a, W, H), bitmap(b, W, H)) == -1
+    assert lo(0, bitmap(a, W, H), bitmap(b, W, H), num=3) == -1
+    assert lo(0, bitmap(a, W, H), bitmap(b, W, H), length=0) == -1
+    assert lo(0, bitmap(a, W, H + 1), bitmap(b, W, H)) == -2
+    assert lo(0, bitmap(a, W, H), bitmap(b, W, H), nb=ln - 1) == -4
+
+
+def test_layout_argument_errors():
+    a, b, w = HostBuf(1 << 20), HostBuf(1 << 20), HostBuf(1 << 22)
+    L = M._lib
+    W, H = 100, 30
+    assert L.morph_layout_rle_workspace_bytes(W, H, 1, 1000) > 0
+    assert L.morph_layout_rle_workspace_bytes(0, H, 1, 1000) == 0
+    assert L.morph_layout_rle_workspace_bytes(W, H, 1, -1) == 0
+    sp = (ctypes.c_int32 * 2)()
+    cap = M.morph_rle_max_runs(W, H)
+    call = lambda s_, d, num=1, den=3, conn=8, nb=1 << 20: L.morph_layout_rle(
+        ctypes.byref(s_), num, den, conn, ctypes.byref(d), None, 0, None, None, 0, sp,
+        (w.ptr + 255) & ~255, nb, None)
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), num=0) == -1
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), num=4, den=3) == -1
+    assert call(rle(a, W, H, cap), rle(b, W + 1, H, cap)) == -2
+    assert call(rle(a, W, H, cap), rle(b, W, H, cap), nb=16) == -4

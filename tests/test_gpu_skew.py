@@ -97,10 +97,11 @@ def test_rotation_matches_oracle(angle):
     # tan(a/2) and sin(a) over 2^16, computed here and not by the binding
     den = 1 << 16
     tn, sn = int(round(math.tan(angle / 2) * den)), int(round(math.sin(angle) * den))
+    assert M.rotation_rationals(angle) == (tn, sn, den)
     want = osh.rotate(img, tn, sn, den)
     pk, rl = both(img)
-    assert_img(M.rotate(pk, tn, sn, den), want, "packed %.2f" % angle)
-    assert_img(M.rotate(rl, tn, sn, den), want, "runs %.2f" % angle)
+    assert_img(M.rotate(pk, angle), want, "packed %.2f" % angle)
+    assert_img(M.rotate(rl, angle), want, "runs %.2f" % angle)
 
 
 @pytest.mark.parametrize("op", ["erode", "dilate"])
@@ -122,3 +123,19 @@ def test_line_op_letter_page():
         want = osh.line_op(op, img, 21, 1, 2)
         assert_img(M.line_op(op, pk, 21, 1, 2), want, "packed " + op)
         assert_img(M.line_op(op, rl, 21, 1, 2), want, "runs " + op)
+
+
+def test_compositions_on_stacked_pages():
+    """Skews, rotation and a line operation over three stacked pages: every
+    page on its own, as the oracle does it page by page."""
+    P, H, W = 3, 50, 90
+    pages = [blobs_img(60 + k, H, W, 0.4) for k in range(P)]
+    pk, rl = both(np.concatenate(pages), P)
+    den = 1 << 16
+    tn, sn = int(round(math.tan(0.3) * den)), int(round(math.sin(0.6) * den))
+    for src in (pk, rl):
+        got, _ = M.skew_cols(src, -3, 5, 40)
+        assert_img(got, np.concatenate([osh.skew_cols(p, -3, 5, 40)[0] for p in pages]), "skew cols")
+        assert_img(M.rotate(src, 0.6), np.concatenate([osh.rotate(p, tn, sn, den) for p in pages]), "rotate")
+        assert_img(M.line_op("dilate", src, 9, 2, 3),
+                   np.concatenate([osh.line_op("dilate", p, 9, 2, 3) for p in pages]), "line")
