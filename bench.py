@@ -809,6 +809,20 @@ def main():
     packed_jobs = [(op, name, se) for name, se in LETTER_SES for op in OPS]
     do_packed = args.only in ("all", "packed")
     do_rle = args.only in ("all", "rle")
+    # the strategy of each operation on runs, picked by the autotuner from
+    # timings on this batch (untimed): within lines then between lines, or
+    # within lines along the rows and the columns around a transposition
+    from paper_0712_0121_amd.tune import Tuner
+    tuner = Tuner(device="cuda:0")
+    strategy = {}
+    ws_rlet = None
+    if do_rle:
+        M.morph_pack_to_rle(rle_src, src, ws_p2r)
+        tuner.tune_strategy(rle_src, [(op, se) for op, _, se in packed_jobs])
+        strategy = {(op, name): tuner.choose_strategy(op, se) for op, name, se in packed_jobs}
+        n_t = max([0] + [M.morph_rlet_workspace_bytes(op, W, H, B, se) for op, name, se in packed_jobs
+                         if strategy[(op, name)] == "transpose"])
+        ws_rlet = torch.empty(n_t, dtype=torch.uint8, device=dev) if n_t else None
 
     def step(ev=None):
         if do_packed:
@@ -824,10 +838,13 @@ def main():
             M.morph_pack_to_rle(rle_src, src, ws_p2r)
             if ev is not None:
                 ev["p2r"][1].record(stream)
-            for k, (op, _, se) in enumerate(packed_jobs):
+            for k, (op, name, se) in enumerate(packed_jobs):
                 if ev is not None:
                     ev["rle"][k][0].record(stream)
-                M.RLE_OPS[op](rle_dst, rle_src, se, ws_rle)
+                if strategy[(op, name)] == "transpose":
+                    M.morph_rect_rlet(op, rle_dst, rle_src, se, ws_rlet)
+                else:
+                    M.RLE_OPS[op](rle_dst, rle_src, se, ws_rle)
                 if ev is not None:
                     ev["rle"][k][1].record(stream)
             if ev is not None:
@@ -952,6 +969,7 @@ def main():
                             "gpixel_s": n_ops * B * page_px / ((sum(rle_ms) + p2r + r2p) / 1e3) / 1e9,
                             "ms_per_op": {"%s %s" % (op, name): round(m, 4)
                                           for (op, name, _), m in zip(packed_jobs, rle_ms)},
+                            "strategy": {"%s %s" % k: v for k, v in strategy.items()},
                             "runs_in": int(rle_src.row_ptr[-1].item())}
     out["breakdown"] = breakdown
     out["copy_ceiling_gbs"] = copy_gbs
@@ -1013,14 +1031,12 @@ def main():
                                                                   "p99": percentile(lat_g, 99)},
                                   "reps": args.latency_reps}
     if args.only == "all" and not args.no_extras:
-        del rle_src, rle_dst, ws_rle
+        del rle_src, rle_dst, ws_rle, ws_rlet
         torch.cuda.empty_cache()
-        from paper_0712_0121_amd.tune import Tuner
-        tuner = Tuner(device="cuda:0")
-        # serving first: its latencies depend on the host's state (pinned
-        # pools, allocator caches), which the other extras leave loaded
-        # the representation table first: the batch and the serving
-        # executor route pages by it
+        # the representation table first (the batch and the serving executor
+        # route pages by it), then serving, whose latencies depend on the
+        # host's state (pinned pools, allocator caches), which the other
+        # extras leave loaded
         out["repr_choice"] = bench_repr(M, dev, tuner)
         out["serving"] = bench_serving(M, dev, args.serve_seconds, tuner)
         out["batched"] = bench_batched(M, dev, tuner)

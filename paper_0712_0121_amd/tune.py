@@ -49,6 +49,13 @@ def shape_key(W, H, op, se):
     return "s%d_h%d_n%d" % (bucket((W + 63) // 64, STRIDE_BUCKETS), bucket(h, H_BUCKETS), nst)
 
 
+W_BUCKETS = (1, 4, 16, 64, 1 << 30)        # element widths up to each bound
+
+
+def strategy_key(op, se):
+    return "%s_w%d_h%d" % (op, bucket(se[0], W_BUCKETS), bucket(se[1], H_BUCKETS))
+
+
 def repr_key(density, op, se):
     return "d%d_%s_k%d" % (bucket(density, DENSITY_BUCKETS), op, bucket(max(se[0], se[1]), SIZE_CLASSES))
 
@@ -57,7 +64,7 @@ class Tuner:
     def __init__(self, cache_path: str | None = None, device="cuda:0"):
         self.path = cache_path or os.environ.get("MORPH_TUNE_CACHE", DEFAULT_CACHE)
         self.device = device
-        self.table = {"shape": {}, "repr": {}}
+        self.table = {"shape": {}, "repr": {}, "strategy": {}}
         self.arch = None
         self.load()
 
@@ -74,6 +81,7 @@ class Tuner:
             with open(self.path) as f:
                 data = json.load(f)
             self.table = data.get(self._arch(), self.table) if data else self.table
+            self.table.setdefault("strategy", {})
         except (OSError, ValueError, RuntimeError, AssertionError):
             pass
 
@@ -98,6 +106,13 @@ class Tuner:
         library default."""
         v = self.table["shape"].get(shape_key(W, H, op, se))
         return tuple(v["best"]) if v else (0, 0)
+
+    def choose_strategy(self, op, se):
+        """'lines' (within-line passes, then between-line intersections) or
+        'transpose' (within-line passes along the rows and, after a
+        transposition, along the columns) for an operation on runs."""
+        v = self.table.get("strategy", {}).get(strategy_key(op, se))
+        return v["best"] if v else "lines"
 
     def choose_repr(self, density, op, se):
         """'packed' or 'rle' for a page held packed, conversions included."""
@@ -205,6 +220,38 @@ class Tuner:
             del src, dst, back, r_in, r_out, w_p2r
             torch.cuda.empty_cache()
         return self.table["repr"]
+
+    def tune_strategy(self, src, cases, verbose=False):
+        """The paper's two strategies for rectangles on run-length images
+        (section "2D Morphological Operators for Rectangular Masks"): within
+        lines, then between lines; or within lines along the rows and, after
+        a transposition, along the columns.  Times both for every (op,
+        element) of `cases` on the run-length batch `src` and records the
+        faster per (op, width bucket, height bucket)."""
+        import torch
+        import paper_0712_0121_amd as M
+        dev = src.row_ptr.device
+        W, H, P = src.width, src.height, src.npages
+        dst = M.RLE.empty(W, H, P, device=dev)
+        per_key = {}
+        for op, se in cases:
+            w_l = torch.empty(max(M.morph_rle_workspace_bytes(op, W, H, P, se), 1), dtype=torch.uint8, device=dev)
+            t_l = self._time(lambda: M.RLE_OPS[op](dst, src, se, w_l), 3)
+            del w_l
+            w_t = torch.empty(max(M.morph_rlet_workspace_bytes(op, W, H, P, se), 1), dtype=torch.uint8, device=dev)
+            t_t = self._time(lambda: M.morph_rect_rlet(op, dst, src, se, w_t), 3)
+            del w_t
+            k = strategy_key(op, se)
+            a, b = per_key.get(k, (0.0, 0.0))
+            per_key[k] = (a + t_l, b + t_t)
+        for k, (t_l, t_t) in per_key.items():
+            self.table.setdefault("strategy", {})[k] = {"best": "lines" if t_l <= t_t else "transpose",
+                                                        "lines_ms": t_l, "transpose_ms": t_t, "pages": P}
+            if verbose:
+                print("strategy", k, self.table["strategy"][k])
+        del dst
+        torch.cuda.empty_cache()
+        return self.table["strategy"]
 
     def rle_possible(self, op, se):
         """Whether any density bucket sends (op, element size class) to runs:

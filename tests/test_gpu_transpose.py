@@ -236,3 +236,27 @@ def test_rlet_letter_batch_as_timed(op):
         assert torch.equal(rb.row_ptr, r_in.row_ptr)
         n = int(r_in.row_ptr[-1].item())
         assert torch.equal(rb.runs[:n], r_in.runs[:n])
+
+
+def test_strategy_tuner_times_both_and_both_agree(tmp_path):
+    """The autotuner's choice between the two strategies on runs: it times
+    both on a run-length stack and records the faster per (op, width
+    bucket, height bucket); both strategies give the same runs."""
+    from paper_0712_0121_amd.tune import Tuner, strategy_key
+    pages = [pagegen.letter_page(2000 + i).img for i in range(4)]
+    img = np.concatenate(pages)
+    W, H = 2550, 3300
+    src = M.pack_to_rle(M.Bitmap.from_words(oracle.pack(img), W, npages=4))
+    cases = [("close", (1, 31, 0, 15)), ("erode", (31, 1, 15, 0))]
+    t = Tuner(cache_path=str(tmp_path / "t.json"))
+    tab = t.tune_strategy(src, cases)
+    for op, se in cases:
+        v = tab[strategy_key(op, se)]
+        assert v["lines_ms"] > 0 and v["transpose_ms"] > 0 and v["best"] in ("lines", "transpose")
+        a = M.rect_rle(op, src, se)
+        b = M.rect_rlet(op, src, se)
+        torch.cuda.synchronize()
+        ra, ua = a.to_host()
+        rb, ub = b.to_host()
+        np.testing.assert_array_equal(ra, rb)
+        np.testing.assert_array_equal(ua, ub)

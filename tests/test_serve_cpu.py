@@ -167,3 +167,13 @@ def test_tuner_rle_possible_and_choice(tmp_path):
     assert t.rle_possible("dilate", (3, 11, 1, 5))
     assert not t.rle_possible("erode", (3, 3, 1, 1))
     assert not t.rle_possible("dilate", (3, 3, 1, 1))
+
+
+def test_strategy_lookup_defaults_to_lines(tmp_path):
+    from paper_0712_0121_amd.tune import Tuner, strategy_key
+    t = Tuner(cache_path=str(tmp_path / "s.json"))
+    assert t.choose_strategy("close", (1, 31, 0, 15)) == "lines"
+    t.table["strategy"] = {strategy_key("close", (1, 31, 0, 15)): {"best": "transpose"}}
+    assert t.choose_strategy("close", (1, 25, 0, 12)) == "transpose"     # same width and height buckets
+    assert t.choose_strategy("close", (31, 1, 15, 0)) == "lines"
+    assert t.choose_strategy("open", (1, 31, 0, 15)) == "lines"
