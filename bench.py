@@ -180,6 +180,9 @@ TRAFFIC_SOURCES = {
     "col_scan_kernel": "paper_0712_0121_amd/csrc/rle.hip",
     "pack_to_rle_group_kernel": "paper_0712_0121_amd/csrc/rle.hip",
     "rle_to_pack_group_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "transpose_kernel": "paper_0712_0121_amd/csrc/packed.hip",
+    "decode_transpose_kernel": "paper_0712_0121_amd/csrc/rle.hip",
+    "rle_band_kernel": "paper_0712_0121_amd/csrc/rle_band.hip",
 }
 # The calibration kernel: torch's elementwise bitwise_or of the batch with 0
 # (a plain copy of known size), picked by the functor in its full name so

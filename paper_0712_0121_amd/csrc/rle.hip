@@ -189,6 +189,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
     long long obase = EMIT ? row_ptr[r] : 0;
     int cstart = 0, cend = 0;
     uint64_t prev = 0;                     // bit 63 of the previous chunk's last word
+    int last_start = -1;                   // the last start before this chunk (-1: none)
     for (int j0 = 0; j0 <= nw; j0 += 64) {
         const int j = j0 + lane;
         uint64_t a = 0;
@@ -204,20 +205,26 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
         const int ns = __popcll(st), ne = __popcll(en);
         const int is = wave_incl_scan(ns), ie = wave_incl_scan(ne);
         if (EMIT) {
-            long long k = obase + cstart + is - ns;
-            while (st) {
-                const int b = __ffsll((unsigned long long)st) - 1;
-                if (k < cap) runs[2 * k] = 64 * j + b;
-                k++;
-                st &= st - 1;
+            // each run written whole by the lane of its end (see the
+            // grouped kernel below)
+            int incl = st ? 64 * j + 63 - (int)__clzll(st) : -1;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl = max(incl, y);
             }
-            k = obase + cend + ie - ne;
+            int before = __shfl_up(incl, 1, 64);
+            before = lane == 0 ? last_start : max(last_start, before);
+            long long k = obase + cend + ie - ne;
             while (en) {
                 const int b = __ffsll((unsigned long long)en) - 1;
-                if (k < cap) runs[2 * k + 1] = 64 * j + b;
+                const uint64_t below = st & ((1ull << b) - 1);
+                const int s0 = below ? 64 * j + 63 - (int)__clzll(below) : before;
+                if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, 64 * j + b);
                 k++;
                 en &= en - 1;
             }
+            last_start = max(last_start, __shfl(incl, 63, 64));
         }
         cstart += __shfl(is, 63, 64);
         cend += __shfl(ie, 63, 64);
@@ -461,6 +468,17 @@ __device__ __forceinline__ int group_last(int x)
     return __builtin_amdgcn_update_dpp(0, x, 0x15f, 0xf, 0xf, false);
 }
 
+// Inclusive maximum over the 16 lanes of a group (lanes below the shift
+// read -1, the "none" value of the callers).
+__device__ __forceinline__ int group_incl_max(int x)
+{
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));    // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));    // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));    // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));    // row_shr:8
+    return x;
+}
+
 // ------------------------------------------- packed -> runs, narrow rows
 // The same transitions with one 16-lane group per row (four rows a wave):
 // lane k takes words k, k + 16, ...; the bit before a word comes from the
@@ -483,6 +501,7 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
     const long long obase = EMIT ? row_ptr[r] : 0;
     int cstart = 0, cend = 0;
     int prev = 0;                          // bit 63 of the word before this block
+    int last_start = -1;                   // the last start before this block (-1: none)
     for (int j0 = 0; j0 <= nw; j0 += kGroup) {
         const int j = j0 + gl;
         uint64_t a = 0;
@@ -501,20 +520,23 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
         const int ns = __popcll(st), ne = __popcll(en);
         const int is = group_incl_scan(ns), ie = group_incl_scan(ne);
         if (EMIT) {
-            long long k = obase + cstart + is - ns;
-            while (st) {
-                const int b = __ffsll((unsigned long long)st) - 1;
-                if (k < cap) runs[2 * k] = 64 * j + b;
-                k++;
-                st &= st - 1;
-            }
-            k = obase + cend + ie - ne;
+            // every run is written whole, as one pair, by the lane that holds
+            // its end: its start is the nearest start bit below the end in
+            // the same word, or else the last start of an earlier word (runs
+            // alternate with gaps, so that is the run's own start)
+            const int ls = st ? 64 * j + 63 - (int)__clzll(st) : -1;
+            const int incl = group_incl_max(ls);
+            const int before = max(last_start, __builtin_amdgcn_update_dpp(-1, incl, 0x111, 0xf, 0xf, false));
+            long long k = obase + cend + ie - ne;
             while (en) {
                 const int b = __ffsll((unsigned long long)en) - 1;
-                if (k < cap) runs[2 * k + 1] = 64 * j + b;
+                const uint64_t below = st & ((1ull << b) - 1);
+                const int s0 = below ? 64 * j + 63 - (int)__clzll(below) : before;
+                if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, 64 * j + b);
                 k++;
                 en &= en - 1;
             }
+            last_start = max(last_start, group_last(incl));
         }
         cstart += group_last(is);
         cend += group_last(ie);
