@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed batch, serving and representation measurements")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--sequential", action="store_true",
+                    help="run the packed and the run-length operations of a timed step on one stream")
     g = ap.add_argument_group("profile summary (no GPU): rocprofv3 CSV output -> markdown")
     g.add_argument("--summarize-profile", action="store_true")
     g.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output directory")
@@ -827,8 +829,19 @@ def main():
                          if strategy[(op, name)] == "transpose"])
         ws_rlet = torch.empty(n_t, dtype=torch.uint8, device=dev) if n_t else None
 
-    def step(ev=None):
-        if do_packed:
+    side = torch.cuda.Stream(device=dev)       # default priority
+
+    def step(ev=None, conc=False):
+        # conc: the packed operations run on a second stream beside the
+        # run-length chain (independent inputs and outputs), joined at the end
+        cur = torch.cuda.current_stream()
+        conc = conc and do_packed and do_rle and ev is None
+        if conc:
+            side.wait_stream(cur)
+            with torch.cuda.stream(side):
+                for op, _, se in packed_jobs:
+                    M.PACKED[op](dst, src, se, ws_pk)
+        elif do_packed:
             for k, (op, _, se) in enumerate(packed_jobs):
                 if ev is not None:
                     ev["pk"][k][0].record(stream)
@@ -855,19 +868,22 @@ def main():
             M.morph_rle_to_pack(back, rle_dst)
             if ev is not None:
                 ev["r2p"][1].record(stream)
+        if conc:
+            cur.wait_stream(side)
 
     def new_events():
         E = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         return {"pk": [E() for _ in packed_jobs], "rle": [E() for _ in packed_jobs], "p2r": E(), "r2p": E()}
 
+    conc = not args.sequential
     for _ in range(args.warmup):
-        step()
+        step(conc=conc)
     torch.cuda.synchronize()
-    # the timed steps: nothing but the library calls on the stream
+    # the timed steps: nothing but the library calls on the stream(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step()
+        step(conc=conc)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # the same step captured once into a HIP graph and replayed (no entry
@@ -878,7 +894,7 @@ def main():
     eager_out = [t.clone() for t in outs()]
     g_step = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g_step):
-        step()
+        step(conc=conc)
     for _ in range(args.warmup):
         g_step.replay()
     torch.cuda.synchronize()
@@ -889,6 +905,15 @@ def main():
     dt_graph = time.perf_counter() - tg
     graph_check["identical"] = all(bool(torch.equal(a, b)) for a, b in zip(eager_out, outs()))
     del g_step, eager_out
+    # the same steps with both paths on one stream, for comparison
+    dt_seq = None
+    if conc and do_packed and do_rle:
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for s in range(args.steps):
+            step(conc=False)
+        torch.cuda.synchronize()
+        dt_seq = time.perf_counter() - tq
     # the same steps again, with HIP events around every operation and the
     # library's launch tracing, for the per-operation and per-kernel figures
     evs = [new_events() for _ in range(args.steps)]
@@ -929,6 +954,8 @@ def main():
         "unit": "Gpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "ms_per_step_graph": dt_graph * 1e3 / args.steps, "graph_outputs_identical": graph_check["identical"],
+        "paths_on_two_streams": conc and do_packed and do_rle,
+        "ms_per_step_one_stream": dt_seq * 1e3 / args.steps if dt_seq is not None else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+i32",
         "data": "synthetic (seeded letter pages, %d distinct, resident in HBM)" % args.distinct,
         "config": {"workload": "letter page 2550x3300 (40 words/row), batch of %d pages; erode, dilate, "
