@@ -91,7 +91,7 @@ class morph_kernel_trace_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-MORPH_K_COUNT = 19
+MORPH_K_COUNT = 20
 
 
 class morph_page_desc_t(ctypes.Structure):

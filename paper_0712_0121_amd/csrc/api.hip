@@ -681,10 +681,23 @@ static bool transposed_shape(int dw, int dh, int dp, int sw, int sh, int sp)
 // Workspace of a run-length transpose: the transposed bitmap, the scratch
 // of the re-encoding, then the source decoded in its own orientation (rows
 // of up to 128 words are decoded there and transposed as a bitmap).
+// Whether the runs of the transpose of a W x H image (P pages) are encoded
+// straight from the decoded bitmap in its own orientation (rows of up to
+// 128 words), without the transposed bitmap.
+static bool direct_transposed(int W, int H, int P)
+{
+    const long long pieces = (long long)W * P * ((H + 511) / 512);
+    return (W + 63) / 64 <= 128 && pieces < 0x7fffffffLL;
+}
+
+// Workspace of the run-length transpose: the transposed bitmap (the path
+// through it only), the encoding scratch of either path, and the decoded
+// image in its own orientation.
 static size_t transpose_rle_ws(int W, int H, int P)
 {
     const size_t rows = (size_t)W * P;
-    return round256(image_bytes(H, (int)rows)) + round256(morph_pack_to_rle_workspace_bytes(H, (int)rows)) +
+    return round256(image_bytes(H, (int)rows)) +
+           round256(std::max(morph_pack_to_rle_workspace_bytes(H, (int)rows), transposed_rle_workspace(W, H, P))) +
            round256(image_bytes(W, H * P));
 }
 
@@ -707,12 +720,16 @@ static RletWs rlet_ws(int op, int W, int H, int P, morph_se_t se)
     w.cap = rowsT * ((H + 1) / 2);
     w.rp = round256((size_t)(rowsT + 1) * 4);
     w.runs = round256(std::max((size_t)w.cap * 8, image_bytes(W, (int)rows)));
-    w.p2r = round256(std::max(morph_pack_to_rle_workspace_bytes(H, (int)rowsT),
-                              morph_pack_to_rle_workspace_bytes(W, (int)rows)));
+    w.p2r = round256(std::max({morph_pack_to_rle_workspace_bytes(H, (int)rowsT),
+                               morph_pack_to_rle_workspace_bytes(W, (int)rows), transposed_rle_workspace(W, H, P),
+                               transposed_rle_workspace(H, W, P)}));
     if (op == MORPH_OPEN || op == MORPH_CLOSE) {
-        const morph_se_t row{se.w, 1, se.cx, 0};
-        w.rowop = round256(morph_workspace_bytes(op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE, MORPH_PACKED,
-                                                 W, (int)rows, row));
+        // the last within-line pass along the rows, on the image in its own
+        // orientation or, as a pass along the columns, on its transpose
+        const int op2 = op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE;
+        const morph_se_t row{se.w, 1, se.cx, 0}, col{1, se.w, 0, se.cx};
+        w.rowop = round256(std::max(morph_workspace_bytes(op2, MORPH_PACKED, W, (int)rows, row),
+                                    morph_workspace_bytes(op2, MORPH_PACKED, H, (int)rowsT, col)));
     }
     // each decode's source in its own orientation, before the transpose
     w.tmp = round256(std::max(image_bytes(W, (int)rows), image_bytes(H, (int)rowsT)));
@@ -746,15 +763,42 @@ static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morp
     default: col = LineOp{kLineOpen, se.h, se.h - 1 - se.cy, 1}; break;   // closing: the gaps' opening
     }
     uint64_t *tmp = (uint64_t *)(ws + L.bm + L.rp + L.runs + L.p2r + L.rowop);
-    hipError_t e = rle_decode_transposed(T1, src, row, s, tmp);
-    if (e == hipSuccess) e = rle_from_packed(R1, T1, p2r, s);
-    if (e == hipSuccess) e = rle_decode_transposed(T2, R1, col, s, tmp);
-    if (e == hipSuccess && (op == MORPH_ERODE || op == MORPH_DILATE)) e = rle_from_packed(dst, T2, p2r, s);
+    const bool one = (op == MORPH_ERODE || op == MORPH_DILATE);
+    hipError_t e;
+    // each decode into tmp in the runs' own orientation, then the runs of
+    // its transpose encoded straight from it (where the rows allow)
+    if (direct_transposed(W, H, P)) {
+        const morph_bitmap_t D{tmp, W, H, (W + 63) / 64, P};
+        e = rle_decode_rows(D, src, row, s);
+        if (e == hipSuccess) e = rle_from_packed_transposed(R1, D, p2r, s);
+    } else {
+        e = rle_decode_transposed(T1, src, row, s, tmp);
+        if (e == hipSuccess) e = rle_from_packed(R1, T1, p2r, s);
+    }
+    const int op2 = op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE;
+    void *rowop_ws = L.rowop ? ws + L.bm + L.rp + L.runs + L.p2r : nullptr;
+    if (e == hipSuccess && direct_transposed(H, W, P)) {
+        const morph_bitmap_t D{tmp, H, W, (H + 63) / 64, P};
+        e = rle_decode_rows(D, R1, col, s);
+        if (e == hipSuccess && one) e = rle_from_packed_transposed(dst, D, p2r, s);
+        if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+        if (one) return MORPH_OK;
+        // opening and closing: the last pass along the rows runs down the
+        // columns of the decoded transpose, which is then encoded back
+        const morph_bitmap_t V{(uint64_t *)ws, H, W, (H + 63) / 64, P};
+        const int rc = rect_packed(op2, &V, &D, morph_se_t{1, se.w, 0, se.cx}, rowop_ws, L.rowop, s);
+        if (rc != MORPH_OK) return rc;
+        e = rle_from_packed_transposed(dst, V, p2r, s);
+        if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
+        return MORPH_OK;
+    } else if (e == hipSuccess) {
+        e = rle_decode_transposed(T2, R1, col, s, tmp);
+        if (e == hipSuccess && one) e = rle_from_packed(dst, T2, p2r, s);
+    }
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
-    if (op == MORPH_ERODE || op == MORPH_DILATE) return MORPH_OK;
+    if (one) return MORPH_OK;
     const morph_se_t last{se.w, 1, se.cx, 0};
-    const int rc = rect_packed(op == MORPH_OPEN ? MORPH_DILATE : MORPH_ERODE, &T3, &T2, last,
-                               L.rowop ? ws + L.bm + L.rp + L.runs + L.p2r : nullptr, L.rowop, s);
+    const int rc = rect_packed(op2, &T3, &T2, last, rowop_ws, L.rowop, s);
     if (rc != MORPH_OK) return rc;
     e = rle_from_packed(dst, T3, p2r, s);
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
@@ -804,11 +848,19 @@ int morph_transpose_rle(const morph_rle_t *dst, const morph_rle_t *src, void *ws
     const int W = src->width, H = src->height, P = src->npages;
     char *w = (char *)ws;
     const morph_bitmap_t T{(uint64_t *)w, H, W, (H + 63) / 64, P};
-    uint64_t *tmp = (uint64_t *)(w + round256(image_bytes(H, W * P)) +
-                                 round256(morph_pack_to_rle_workspace_bytes(H, W * P)));
-    hipError_t e = rle_decode_transposed(T, *src, LineOp{kLineNone, 1, 0, 0}, (hipStream_t)stream, tmp);
-    if (e == hipSuccess)
-        e = rle_from_packed(*dst, T, w + round256(image_bytes(H, W * P)), (hipStream_t)stream);
+    char *enc = w + round256(image_bytes(H, W * P));
+    uint64_t *tmp = (uint64_t *)(enc + round256(std::max(morph_pack_to_rle_workspace_bytes(H, W * P),
+                                                         transposed_rle_workspace(W, H, P))));
+    const LineOp none{kLineNone, 1, 0, 0};
+    hipError_t e;
+    if (direct_transposed(W, H, P)) {
+        const morph_bitmap_t D{tmp, W, H, (W + 63) / 64, P};
+        e = rle_decode_rows(D, *src, none, (hipStream_t)stream);
+        if (e == hipSuccess) e = rle_from_packed_transposed(*dst, D, enc, (hipStream_t)stream);
+    } else {
+        e = rle_decode_transposed(T, *src, none, (hipStream_t)stream, tmp);
+        if (e == hipSuccess) e = rle_from_packed(*dst, T, enc, (hipStream_t)stream);
+    }
     if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
     return MORPH_OK;
 }
@@ -1167,7 +1219,8 @@ const char *morph_kernel_name(int k)
                                                "decode_transpose_kernel", "components",
                                                "component_stats_kernel", "run_hist_kernel", "mask_kernel",
                                                "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel",
-                                               "col_scan_kernel", "rle_band_kernel", "rle_band_count_kernel"};
+                                               "col_scan_kernel", "rle_band_kernel", "rle_band_count_kernel",
+                                               "transposed_to_rle_kernel"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

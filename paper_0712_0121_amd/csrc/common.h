@@ -208,6 +208,15 @@ struct LineOp {
 // up to 128 words (decode, then transpose); nullptr keeps the direct decode.
 hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op,
                                  hipStream_t stream, uint64_t *tmp = nullptr);
+// Runs -> packed bitmap in the runs' own orientation, with op applied along
+// the rows (rows of up to 128 words).
+hipError_t rle_decode_rows(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op, hipStream_t stream);
+// The runs of the transpose of a packed bitmap (dst: width = src height,
+// height = src width), encoded without the transposed bitmap; ws holds
+// transposed_rle_workspace(src width, src height, npages) bytes, 256-aligned.
+size_t transposed_rle_workspace(int W, int H, int P);
+hipError_t rle_from_packed_transposed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
+                                      hipStream_t stream);
 int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
 
 void set_hip_error(hipError_t e);

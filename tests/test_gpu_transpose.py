@@ -75,7 +75,13 @@ def test_transpose_packed_stacked_pages_and_letter_page():
 
 
 # -------------------------------------------------------------- run-length
-@pytest.mark.parametrize("hw", SIZES, ids=lambda s: "%dx%d" % s)
+# and for the runs: columns of several 512-row tiles (a multiple of 64 tall,
+# so that a column black to the bottom ends past the last block), rows of
+# more than 128 words (decoded straight into the transposed bitmap)
+RLE_SIZES = SIZES + [(1024, 70), (1100, 600), (513, 3), (20, 9000)]
+
+
+@pytest.mark.parametrize("hw", RLE_SIZES, ids=lambda s: "%dx%d" % s)
 def test_transpose_rle(hw):
     H, W = hw
     for p in (0.0, 0.3, 0.9, 1.0):
@@ -187,10 +193,12 @@ def test_trace_names_the_transpose_kernels():
         M.transpose_packed(bitmap_gpu(img))
     res = tr.result
     assert res["decode_transpose_kernel"]["launches"] == 2
-    # rows of up to 128 words are decoded in their own orientation and turned
-    # by the bit-block transpose: one in each decode, one called directly
-    assert res["transpose_kernel"]["launches"] == 3
-    assert res["pack_to_rle_kernel"]["launches"] == 2
+    # rows of up to 128 words are decoded in their own orientation and the
+    # runs of the transpose encoded from that bitmap: no transposed bitmap
+    # (the one bit-block transpose is the direct call)
+    assert res["transpose_kernel"]["launches"] == 1
+    assert res["transposed_to_rle_kernel"]["launches"] == 2
+    assert "pack_to_rle_kernel" not in res
     n = int(src.nruns())
     # algorithmic bytes of the first decode: the runs and row counts read,
     # the page's words written (5 words x 100 rows)
