@@ -185,7 +185,6 @@ TRAFFIC_SOURCES = {
     "transpose_kernel": "paper_0712_0121_amd/csrc/packed.hip",
     "decode_transpose_kernel": "paper_0712_0121_amd/csrc/rle.hip",
     "rle_band_kernel": "paper_0712_0121_amd/csrc/rle_band.hip",
-    "transposed_to_rle_kernel": "paper_0712_0121_amd/csrc/rle.hip",
 }
 # The calibration kernel: torch's elementwise bitwise_or of the batch with 0
 # (a plain copy of known size), picked by the functor in its full name so

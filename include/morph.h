@@ -552,7 +552,8 @@ enum {
     MORPH_K_RLE_BAND = 17,     /* run-length rectangle operation, one band per workgroup in LDS:
                                   the launch that writes the runs */
     MORPH_K_RLE_BAND_COUNT = 18, /* the same, the launch that counts each output row's runs */
-    MORPH_K_TRANSPOSE_TO_RLE = 19, /* bitmap -> runs of its transpose (count and emit launches) */
+    MORPH_K_TRANSPOSE_TO_RLE = 19, /* bitmap -> runs of its transpose: the transpose with the run
+                                     counts of its rows, the scan, the emit launch */
     MORPH_K_COUNT = 20
 };
 typedef struct {

@@ -681,13 +681,13 @@ static bool transposed_shape(int dw, int dh, int dp, int sw, int sh, int sp)
 // Workspace of a run-length transpose: the transposed bitmap, the scratch
 // of the re-encoding, then the source decoded in its own orientation (rows
 // of up to 128 words are decoded there and transposed as a bitmap).
-// Whether the runs of the transpose of a W x H image (P pages) are encoded
-// straight from the decoded bitmap in its own orientation (rows of up to
-// 128 words), without the transposed bitmap.
+// Whether the runs of the transpose of a W x H image (P pages) take the
+// short path: the runs decoded into a bitmap in their own orientation (rows
+// of up to 128 words), its transpose made together with the run counts of
+// its rows (rows of up to 128 words too), and the runs encoded from it.
 static bool direct_transposed(int W, int H, int P)
 {
-    const long long pieces = (long long)W * P * ((H + 511) / 512);
-    return (W + 63) / 64 <= 128 && pieces < 0x7fffffffLL;
+    return (W + 63) / 64 <= 128 && (H + 63) / 64 <= 128 && (long long)W * P < 0x7fffffffLL;
 }
 
 // Workspace of the run-length transpose: the transposed bitmap (the path
@@ -770,7 +770,7 @@ static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morp
     if (direct_transposed(W, H, P)) {
         const morph_bitmap_t D{tmp, W, H, (W + 63) / 64, P};
         e = rle_decode_rows(D, src, row, s);
-        if (e == hipSuccess) e = rle_from_packed_transposed(R1, D, p2r, s);
+        if (e == hipSuccess) e = rle_from_packed_transposed(R1, D, (uint64_t *)ws, p2r, s);
     } else {
         e = rle_decode_transposed(T1, src, row, s, tmp);
         if (e == hipSuccess) e = rle_from_packed(R1, T1, p2r, s);
@@ -780,7 +780,7 @@ static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morp
     if (e == hipSuccess && direct_transposed(H, W, P)) {
         const morph_bitmap_t D{tmp, H, W, (H + 63) / 64, P};
         e = rle_decode_rows(D, R1, col, s);
-        if (e == hipSuccess && one) e = rle_from_packed_transposed(dst, D, p2r, s);
+        if (e == hipSuccess && one) e = rle_from_packed_transposed(dst, D, (uint64_t *)ws, p2r, s);
         if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
         if (one) return MORPH_OK;
         // opening and closing: the last pass along the rows runs down the
@@ -788,7 +788,7 @@ static int rlet_run(int op, const morph_rle_t &dst, const morph_rle_t &src, morp
         const morph_bitmap_t V{(uint64_t *)ws, H, W, (H + 63) / 64, P};
         const int rc = rect_packed(op2, &V, &D, morph_se_t{1, se.w, 0, se.cx}, rowop_ws, L.rowop, s);
         if (rc != MORPH_OK) return rc;
-        e = rle_from_packed_transposed(dst, V, p2r, s);
+        e = rle_from_packed_transposed(dst, V, tmp, p2r, s);
         if (e != hipSuccess) { set_hip_error(e); return MORPH_E_HIP; }
         return MORPH_OK;
     } else if (e == hipSuccess) {
@@ -856,7 +856,7 @@ int morph_transpose_rle(const morph_rle_t *dst, const morph_rle_t *src, void *ws
     if (direct_transposed(W, H, P)) {
         const morph_bitmap_t D{tmp, W, H, (W + 63) / 64, P};
         e = rle_decode_rows(D, *src, none, (hipStream_t)stream);
-        if (e == hipSuccess) e = rle_from_packed_transposed(*dst, D, enc, (hipStream_t)stream);
+        if (e == hipSuccess) e = rle_from_packed_transposed(*dst, D, (uint64_t *)w, enc, (hipStream_t)stream);
     } else {
         e = rle_decode_transposed(T, *src, none, (hipStream_t)stream, tmp);
         if (e == hipSuccess) e = rle_from_packed(*dst, T, enc, (hipStream_t)stream);
@@ -1220,7 +1220,7 @@ const char *morph_kernel_name(int k)
                                                "component_stats_kernel", "run_hist_kernel", "mask_kernel",
                                                "mask_and_kernel", "shift_rows_kernel", "shift_rows_rle_kernel",
                                                "col_scan_kernel", "rle_band_kernel", "rle_band_count_kernel",
-                                               "transposed_to_rle_kernel"};
+                                               "transpose_to_rle"};
     return (k >= 0 && k < MORPH_K_COUNT) ? names[k] : "?";
 }
 

@@ -22,10 +22,13 @@ __device__ __forceinline__ unsigned xcd_block()
 }
 
 // Value of lane (this lane ^ J) for J = 1, 2, 4, 8 (DPP moves inside the
-// 16-lane rows), 16 (swizzle inside 32-lane halves) and 32 (permute).
+// 16-lane rows) and 16 (gfx950's v_permlane16_swap: with both operands v it
+// returns, for every lane, row 2k of v in its first and row 2k + 1 in its
+// second result, k = lane / 32).
 template <int J>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
 {
+    static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16, "lane distance");
     if constexpr (J == 1) {
         return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
     } else if constexpr (J == 2) {
@@ -37,27 +40,44 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
         return (threadIdx.x & 4) ? below : above;
     } else if constexpr (J == 8) {
         return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
-    } else if constexpr (J == 16) {
-        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);                       // xor 16
     } else {
-        return (uint32_t)__shfl_xor((int)v, 32, 64);
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
     }
 }
 
+// 32-bit bit select: bits of a where k is 1, of b where it is 0 (v_bfi).
+__device__ __forceinline__ uint32_t bitsel(uint32_t k, uint32_t a, uint32_t b) { return (a & k) | (b & ~k); }
+
+// One butterfly step: the lane without bit J keeps the bits of m and takes
+// its partner's other bits shifted up by J; the lane with bit J keeps the
+// bits of ~m and takes its partner's shifted down.  Written branch-free (a
+// per-lane all-ones/zero mask and bit selects): as a conditional, both arms
+// are taken by half the lanes each and the wave runs both.
 template <int J>
 __device__ __forceinline__ uint64_t transpose_step(uint64_t x, uint64_t m)
 {
     const uint64_t y = ((uint64_t)lane_xor<J>((uint32_t)(x >> 32)) << 32) | lane_xor<J>((uint32_t)x);
-    return (threadIdx.x & J) ? ((x & ~m) | ((y >> J) & m)) : ((x & m) | ((y << J) & ~m));
+    const uint64_t up = 0ull - (uint64_t)((threadIdx.x / J) & 1u);      // all ones on the lane with bit J
+    const uint64_t keep = m ^ up;                                       // the bits this lane keeps
+    const uint64_t dn = y >> J, upv = y << J;
+    const uint64_t ys = ((uint64_t)bitsel((uint32_t)(up >> 32), (uint32_t)(dn >> 32), (uint32_t)(upv >> 32)) << 32) |
+                        bitsel((uint32_t)up, (uint32_t)dn, (uint32_t)upv);
+    return ((uint64_t)bitsel((uint32_t)(keep >> 32), (uint32_t)(x >> 32), (uint32_t)(ys >> 32)) << 32) |
+           bitsel((uint32_t)keep, (uint32_t)x, (uint32_t)ys);
 }
 
 // Transposes the 64 x 64 bit matrix a wave holds one row per lane (bit k of
 // lane i is element (i, k)): afterwards lane i holds column i.  Six steps;
 // step J exchanges the off-diagonal J x J blocks of every 2J x 2J block
-// between lanes i and i ^ J.  Every lane of the wave must be active.
+// between lanes i and i ^ J.  For J = 32 those blocks are whole 32-bit
+// halves: the high half of lanes 0..31 trades places with the low half of
+// lanes 32..63, which is one v_permlane32_swap of (low, high).  Every lane
+// of the wave must be active.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x)
 {
-    x = transpose_step<32>(x, 0x00000000ffffffffull);
+    const auto h = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)(x >> 32), false, false);
+    x = ((uint64_t)h[1] << 32) | h[0];
     x = transpose_step<16>(x, 0x0000ffff0000ffffull);
     x = transpose_step<8>(x, 0x00ff00ff00ff00ffull);
     x = transpose_step<4>(x, 0x0f0f0f0f0f0f0f0full);
@@ -126,6 +146,12 @@ hipError_t popcount_pages(const morph_bitmap_t &src, unsigned long long *counts,
 // Transpose of every page of a packed bitmap (dst: width = src height,
 // height = src width).
 hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream);
+// The same (untraced), also writing the number of runs that start in each
+// piece of every transposed row: counts[row * transpose_pieces(src height)
+// + piece], the pieces of a row being consecutive ranges of its pixels.
+int transpose_pieces(int height);
+hipError_t packed_transpose_counted(const morph_bitmap_t &dst, const morph_bitmap_t &src, int *counts,
+                                    hipStream_t stream);
 
 // ------------------------------------------------------------ arbitrary masks
 // The horizontal runs of a mask as offsets from its origin: run q covers
@@ -212,10 +238,12 @@ hipError_t rle_decode_transposed(const morph_bitmap_t &dst, const morph_rle_t &s
 // the rows (rows of up to 128 words).
 hipError_t rle_decode_rows(const morph_bitmap_t &dst, const morph_rle_t &src, LineOp op, hipStream_t stream);
 // The runs of the transpose of a packed bitmap (dst: width = src height,
-// height = src width), encoded without the transposed bitmap; ws holds
+// height = src width, at most 8192): the transpose, with the run counts of
+// its rows, into tbuf (a bitmap of the transpose's shape, stride
+// ceil(src height / 64)), then the runs from there; ws holds
 // transposed_rle_workspace(src width, src height, npages) bytes, 256-aligned.
 size_t transposed_rle_workspace(int W, int H, int P);
-hipError_t rle_from_packed_transposed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws,
+hipError_t rle_from_packed_transposed(const morph_rle_t &dst, const morph_bitmap_t &src, uint64_t *tbuf, void *ws,
                                       hipStream_t stream);
 int rle_validate(const morph_rle_t &r, hipStream_t stream, hipError_t *err);
 

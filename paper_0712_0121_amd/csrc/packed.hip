@@ -528,68 +528,116 @@ int cached_cu_count = 0;
 // the kTrRows / 64 blocks below each other, after which lane i holds that
 // many consecutive words of transposed row 64j + i and stores them
 // contiguously.  Rows are padded by one word in LDS so that the column
-// reads of the butterfly input spread over the banks.
+// reads of the butterfly input spread over the banks.  (A persistent grid
+// walking tile ranges, with the next tile's loads in flight during the
+// butterflies, measured 1.4x slower on the letter batch.)
+//
+// With counts, each lane also counts the runs that start in its words of
+// the transposed row (the pixel before them is bit i of the source row above
+// the tile) and writes the count of its piece of the row to
+// counts[row * tiles_y + tile row]: the run counts of the transpose come
+// with the transpose itself.
 constexpr int kTrRows = 512, kTrWords = 8, kTrPad = kTrWords + 1;
 constexpr int kTrRowsPerThread = kTrRows / 256, kTrColsPerWave = kTrWords / 4, kTrBlocks = kTrRows / 64;
+
+struct TrTile {
+    int page, tx, ty, y0, j0, nj;
+};
+
+__device__ __forceinline__ TrTile tr_tile(long long t, int tiles_y, int tiles_x, int nw)
+{
+    TrTile T;
+    const long long per_page = (long long)tiles_y * tiles_x;
+    T.page = (int)(t / per_page);
+    const int u = (int)(t - (long long)T.page * per_page);
+    T.tx = u / tiles_y;                 // row tiles fastest
+    T.ty = u - T.tx * tiles_y;
+    T.y0 = T.ty * kTrRows;
+    T.j0 = T.tx * kTrWords;
+    T.nj = min(kTrWords, nw - T.j0);
+    return T;
+}
+
+// This thread's rows of a tile (words past the row or the page are 0, the
+// row's pad bits cleared), and with `above` the word of the row above the
+// tile for threads below kTrWords.
+__device__ __forceinline__ void tr_load(const uint64_t *src, const TrTile &T, int H, int sstride, long long spw,
+                                        uint64_t padmask, int nw, uint64_t (&v)[kTrRowsPerThread][kTrWords],
+                                        uint64_t &ab, bool want_above)
+{
+    const uint64_t *sp = src + (long long)T.page * spw;
+#pragma unroll
+    for (int h = 0; h < kTrRowsPerThread; h++) {
+        const int y = T.y0 + (int)threadIdx.x + 256 * h;
+        const uint64_t *q = sp + (long long)y * sstride + T.j0;
+        if (y < H && T.nj == kTrWords && (((uintptr_t)q) & 15) == 0) {
+            const ulonglong2 *q2 = reinterpret_cast<const ulonglong2 *>(q);
+#pragma unroll
+            for (int c = 0; c < kTrWords / 2; c++) {
+                const ulonglong2 w2 = q2[c];
+                v[h][2 * c] = w2.x;
+                v[h][2 * c + 1] = w2.y;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kTrWords; c++) v[h][c] = (y < H && c < T.nj) ? q[c] : 0ull;
+        }
+        // the last word of the row: pad bits are 0 (a select per word: an
+        // index computed at run time would put v in scratch memory)
+#pragma unroll
+        for (int c = 0; c < kTrWords; c++) v[h][c] &= (T.j0 + c == nw - 1) ? padmask : ~0ull;
+    }
+    ab = 0;
+    if (want_above && threadIdx.x < kTrWords) {
+        const int c = (int)threadIdx.x, y = T.y0 - 1;
+        if (y >= 0 && c < T.nj) {
+            ab = sp[(long long)y * sstride + T.j0 + c];
+            if (T.j0 + c == nw - 1) ab &= padmask;
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void transpose_kernel(
     const uint64_t *__restrict__ src, int W, int H, int sstride, long long spw, uint64_t padmask,
     uint64_t *__restrict__ dst, int dstride, long long dpw, int nw, int nk, int tiles_y, int tiles_x,
-    long long ntiles)
+    long long ntiles, int *__restrict__ counts)
 {
     __shared__ uint64_t tile[kTrRows * kTrPad];
+    __shared__ uint64_t above[kTrWords];
     const long long t = xcd_block();
     if (t >= ntiles) return;                // whole workgroup
-    const long long per_page = (long long)tiles_y * tiles_x;
-    const int page = (int)(t / per_page);
-    const int u = (int)(t - (long long)page * per_page);
-    const int tx = u / tiles_y, ty = u - tx * tiles_y;     // row tiles fastest
-    const int y0 = ty * kTrRows, j0 = tx * kTrWords;
-    const int nj = min(kTrWords, nw - j0);
-    const uint64_t *sp = src + (long long)page * spw;
-#pragma unroll
-    for (int h = 0; h < kTrRowsPerThread; h++) {
-        const int r = (int)threadIdx.x + 256 * h, y = y0 + r;
-        uint64_t v[kTrWords];
-        if (y < H && nj == kTrWords) {
-            const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(sp + (long long)y * sstride + j0);
-            if ((((uintptr_t)q) & 15) == 0) {
-#pragma unroll
-                for (int c = 0; c < kTrWords / 2; c++) {
-                    const ulonglong2 w2 = q[c];
-                    v[2 * c] = w2.x;
-                    v[2 * c + 1] = w2.y;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < kTrWords; c++) v[c] = sp[(long long)y * sstride + j0 + c];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kTrWords; c++)
-                v[c] = (y < H && c < nj) ? sp[(long long)y * sstride + j0 + c] : 0ull;
-        }
-        if (j0 + kTrWords >= nw) {          // the last word of the row: pad bits are 0
-            const int c = nw - 1 - j0;
-#pragma unroll
-            for (int cc = 0; cc < kTrWords; cc++)
-                if (cc == c) v[cc] &= padmask;
-        }
-#pragma unroll
-        for (int c = 0; c < kTrWords; c++) tile[r * kTrPad + c] = v[c];
-    }
-    __syncthreads();
+    const bool cnt_on = counts != nullptr;
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-    const int nkk = min(kTrBlocks, nk - y0 / 64);          // row blocks of this tile
+    const TrTile C = tr_tile(t, tiles_y, tiles_x, nw);
+    uint64_t v[kTrRowsPerThread][kTrWords];
+    uint64_t ab;
+    tr_load(src, C, H, sstride, spw, padmask, nw, v, ab, cnt_on);
 #pragma unroll
-    for (int h = 0; h < kTrColsPerWave; h++) {
-        const int jj = kTrColsPerWave * wv + h;     // word column of the tile
+    for (int h = 0; h < kTrRowsPerThread; h++)
+#pragma unroll
+        for (int c = 0; c < kTrWords; c++) tile[((int)threadIdx.x + 256 * h) * kTrPad + c] = v[h][c];
+    if (cnt_on && threadIdx.x < kTrWords) above[threadIdx.x] = ab;
+    __syncthreads();
+    const int nkk = min(kTrBlocks, nk - C.y0 / 64);        // row blocks of this tile
+#pragma unroll
+    for (int hc = 0; hc < kTrColsPerWave; hc++) {
+        const int jj = kTrColsPerWave * wv + hc;         // word column of the tile
         uint64_t o[kTrBlocks];
 #pragma unroll
         for (int kk = 0; kk < kTrBlocks; kk++) o[kk] = wave_transpose64(tile[(64 * kk + lane) * kTrPad + jj]);
-        const int x = 64 * (j0 + jj) + lane;
-        if (jj < nj && x < W) {
-            uint64_t *dp = dst + (long long)page * dpw + (long long)x * dstride + y0 / 64;
+        const int x = 64 * (C.j0 + jj) + lane;
+        if (cnt_on) {                       // rows past the page bottom are 0
+            uint64_t prev = (above[jj] >> lane) & 1ull;
+            int cnt = 0;
+#pragma unroll
+            for (int kk = 0; kk < kTrBlocks; kk++) {
+                cnt += __popcll(o[kk] & ~((o[kk] << 1) | prev));
+                prev = o[kk] >> 63;
+            }
+            if (jj < C.nj && x < W) counts[((long long)C.page * W + x) * tiles_y + C.ty] = cnt;
+        }
+        if (jj < C.nj && x < W) {
+            uint64_t *dp = dst + (long long)C.page * dpw + (long long)x * dstride + C.y0 / 64;
             if (nkk == kTrBlocks && (((uintptr_t)dp) & 15) == 0) {
                 ulonglong2 *q = reinterpret_cast<ulonglong2 *>(dp);
 #pragma unroll
@@ -902,7 +950,8 @@ hipError_t launch_rect_batch(const RectPage *pages_dev, const TileRef *tiles_dev
     return hipGetLastError();
 }
 
-hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream)
+static hipError_t launch_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, int *counts,
+                                   hipStream_t stream)
 {
     const int W = src.width, H = src.height;
     const int nw = (W + 63) / 64, nk = (H + 63) / 64;
@@ -911,12 +960,27 @@ hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src
     if (ntiles <= 0) return hipSuccess;
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
     const uint64_t pad = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
-    trace_before(MORPH_K_TRANSPOSE, stream);
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)ntiles), dim3(256), 0, stream, src.words, W, H,
                        src.stride_words, (long long)src.stride_words * H, pad, dst.words, dst.stride_words,
-                       (long long)dst.stride_words * W, nw, nk, tiles_y, tiles_x, ntiles);
-    trace_after(MORPH_K_TRANSPOSE, stream, 8.0 * src.npages * ((double)nw * H + (double)nk * W));
+                       (long long)dst.stride_words * W, nw, nk, tiles_y, tiles_x, ntiles, counts);
     return hipGetLastError();
+}
+
+hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream)
+{
+    const int nw = (src.width + 63) / 64, nk = (src.height + 63) / 64;
+    trace_before(MORPH_K_TRANSPOSE, stream);
+    const hipError_t e = launch_transpose(dst, src, nullptr, stream);
+    trace_after(MORPH_K_TRANSPOSE, stream, 8.0 * src.npages * ((double)nw * src.height + (double)nk * src.width));
+    return e;
+}
+
+int transpose_pieces(int height) { return (height + kTrRows - 1) / kTrRows; }
+
+hipError_t packed_transpose_counted(const morph_bitmap_t &dst, const morph_bitmap_t &src, int *counts,
+                                    hipStream_t stream)
+{
+    return launch_transpose(dst, src, counts, stream);
 }
 
 bool plan_mask(MaskPage &p, const MaskRunsArg &m)

@@ -170,6 +170,32 @@ __global__ void zero_one_kernel(int *out)
     if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = 0;
 }
 
+// Writes every run that ends in this lane's word as one pair at k, k + 1,
+// ...: the word covers pixels base .. base + 63, st and en are its start and
+// end bits (an end at bit b: pixel b is white, pixel b - 1 black), and a
+// run whose start is not in the word started at `before` (the last start
+// of an earlier word; runs alternate with gaps).  Works on the two 32-bit
+// halves, one end per step.
+__device__ __forceinline__ void emit_word_runs(uint64_t st, uint64_t en, int base, int before, int k, int cap,
+                                               int *__restrict__ runs)
+{
+    const uint32_t st_lo = (uint32_t)st, st_hi = (uint32_t)(st >> 32);
+    uint32_t en_lo = (uint32_t)en, en_hi = (uint32_t)(en >> 32);
+    // the last start of the low half (or the start before the word)
+    const int ls_lo = st_lo ? base + 31 - (int)__clz(st_lo) : before;
+    while (en_lo | en_hi) {
+        const bool lo = en_lo != 0;
+        const uint32_t e = lo ? en_lo : en_hi;
+        const int b = __ffs(e) - 1;
+        const uint32_t below = (lo ? st_lo : st_hi) & ((1u << b) - 1u);
+        const int half = lo ? base : base + 32;
+        const int s0 = below ? half + 31 - (int)__clz(below) : (lo ? before : ls_lo);
+        if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, half + b);
+        k++;
+        if (lo) en_lo = e & (e - 1u); else en_hi = e & (e - 1u);
+    }
+}
+
 // -------------------------------------------------------- packed -> runs
 // One wave per row.  For each word a: a start is a 1 whose left neighbour
 // is 0 (or the left border), an end is a 0 whose left neighbour is 1; the
@@ -187,6 +213,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
     const int page = r / H, y = r - page * H;
     const uint64_t *row = words + (long long)page * page_words + (long long)y * stride;
     long long obase = EMIT ? row_ptr[r] : 0;
+    const int capi = (int)min(cap, 0x7fffffffLL);   // run indices fit in int: row offsets are int
     int cstart = 0, cend = 0;
     uint64_t prev = 0;                     // bit 63 of the previous chunk's last word
     int last_start = -1;                   // the last start before this chunk (-1: none)
@@ -215,15 +242,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
             }
             int before = __shfl_up(incl, 1, 64);
             before = lane == 0 ? last_start : max(last_start, before);
-            long long k = obase + cend + ie - ne;
-            while (en) {
-                const int b = __ffsll((unsigned long long)en) - 1;
-                const uint64_t below = st & ((1ull << b) - 1);
-                const int s0 = below ? 64 * j + 63 - (int)__clzll(below) : before;
-                if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, 64 * j + b);
-                k++;
-                en &= en - 1;
-            }
+            emit_word_runs(st, en, 64 * j, before, (int)(obase + cend + ie - ne), capi, runs);
             last_start = max(last_start, __shfl(incl, 63, 64));
         }
         cstart += __shfl(is, 63, 64);
@@ -499,16 +518,25 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
     const int page = r / H, y = r - page * H;
     const uint64_t *row = words + (long long)page * page_words + (long long)y * stride;
     const long long obase = EMIT ? row_ptr[r] : 0;
+    const int capi = (int)min(cap, 0x7fffffffLL);   // run indices fit in int: row offsets are int
     int cstart = 0, cend = 0;
     int prev = 0;                          // bit 63 of the word before this block
     int last_start = -1;                   // the last start before this block (-1: none)
-    for (int j0 = 0; j0 <= nw; j0 += kGroup) {
+    // the whole row first (every load in flight at once), then its blocks
+    constexpr int kBlk = kNarrowRowWords / kGroup + 1;
+    uint64_t wv[kBlk];
+#pragma unroll
+    for (int m = 0; m < kBlk; m++) {
+        const int j = m * kGroup + gl;
+        wv[m] = j < nw ? row[j] : 0ull;
+        if (j == nw - 1) wv[m] &= padmask;
+    }
+#pragma unroll
+    for (int m = 0; m < kBlk; m++) {
+        const int j0 = m * kGroup;
+        if (j0 > nw) break;                // wave-uniform
         const int j = j0 + gl;
-        uint64_t a = 0;
-        if (j < nw) {
-            a = row[j];
-            if (j == nw - 1) a &= padmask;
-        }
+        const uint64_t a = wv[m];
         const int top = (int)(a >> 63);
         const int up = __builtin_amdgcn_update_dpp(prev, top, 0x111, 0xf, 0xf, false);   // row_shr:1
         const uint64_t sh = (a << 1) | (uint64_t)(unsigned)up;
@@ -517,6 +545,9 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
             st = 0;
             en = 0;
         }
+        // blocks without a transition in all four rows of the wave (the
+        // white space between text lines) change no row's state
+        if (__builtin_amdgcn_ballot_w64((st | en) != 0) == 0) continue;
         const int ns = __popcll(st), ne = __popcll(en);
         const int is = group_incl_scan(ns), ie = group_incl_scan(ne);
         if (EMIT) {
@@ -527,15 +558,7 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
             const int ls = st ? 64 * j + 63 - (int)__clzll(st) : -1;
             const int incl = group_incl_max(ls);
             const int before = max(last_start, __builtin_amdgcn_update_dpp(-1, incl, 0x111, 0xf, 0xf, false));
-            long long k = obase + cend + ie - ne;
-            while (en) {
-                const int b = __ffsll((unsigned long long)en) - 1;
-                const uint64_t below = st & ((1ull << b) - 1);
-                const int s0 = below ? 64 * j + 63 - (int)__clzll(below) : before;
-                if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, 64 * j + b);
-                k++;
-                en &= en - 1;
-            }
+            emit_word_runs(st, en, 64 * j, before, (int)(obase + cend + ie - ne), capi, runs);
             last_start = max(last_start, group_last(incl));
         }
         cstart += group_last(is);
@@ -547,203 +570,18 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
 }
 
 // ---------------------------------------- packed -> runs of the transpose
-// The runs of the transposed image straight from the bitmap, without the
-// transposed bitmap in between, in two launches around a scan.
-//
-// Count launch: a workgroup takes a tile of kTeRows rows x kTeWords words
-// of a page into LDS (with the row above the tile in front) and each wave
-// turns kTeColsPerWave of its word columns by 64 x 64 bit blocks: lane i
-// then holds consecutive 64-pixel pieces of transposed row 64 j + i, bit k
-// being source row 64 kk + k, and counts the runs that start in them,
-// carrying the pixel before each piece.  The tile rows cut every transposed
-// row into pieces; the counts go out piece by piece within a row and row by
-// row, so that their exclusive scan gives each row's first run at the
-// offset of its first piece.
-//
-// Emit launch: a workgroup takes kTeCols whole word columns of a page (all
-// its rows, kTeChunk blocks of 64 rows at a time).  The waves turn the
-// blocks and store them row by row in LDS; then each 16-lane group encodes
-// whole transposed rows from there as the bitmap encoder encodes rows, one
-// word a lane, carrying each row's state from chunk to chunk.  A row's runs
-// are so written in order by one group, as contiguous pieces of one range,
-// which keeps the stores whole cache lines; a lane that stored the bits of
-// one transposed row alone would scatter 8-byte stores over many rows.
-constexpr int kTeRows = 512, kTeWords = 8, kTePad = kTeWords + 1;
-constexpr int kTeBlocks = kTeRows / 64, kTeColsPerWave = kTeWords / 4;
-constexpr int kTeCols = 2;                        // word columns per emit workgroup
-constexpr int kTeChunk = 16;                      // blocks of 64 rows per chunk (one word a lane)
-constexpr int kTeRs = kTeChunk + 1;               // LDS words per transposed row (odd: spreads the banks)
-constexpr int kTeRowsPerGroup = 64 * kTeCols / kGroupsPerBlock;
-static_assert(kTeChunk == kGroup, "one word of a chunk per lane of a group");
-
-// Word j of source row y (0 outside the page or the row, pad bits cleared).
-__device__ __forceinline__ uint64_t tile_word(const uint64_t *sp, int y, int H, int sstride, int j, int nw,
-                                              uint64_t padmask)
+// The run counts of the transposed rows come with the transpose, one per
+// piece of a row (the part a transpose tile covers); this sums each row's
+// pieces.
+__global__ __launch_bounds__(256) void piece_sum_kernel(const int *__restrict__ pieces, int per_row, long long R,
+                                                        int *__restrict__ counts)
 {
-    if (y < 0 || y >= H || j >= nw) return 0ull;
-    const uint64_t v = sp[(long long)y * sstride + j];
-    return j == nw - 1 ? (v & padmask) : v;
-}
-
-__global__ __launch_bounds__(256) void transposed_count_kernel(
-    const uint64_t *__restrict__ src, int W, int H, int sstride, long long spw, uint64_t padmask, int nw,
-    int tiles_y, int tiles_x, long long ntiles, int *__restrict__ piece_cnt)
-{
-    __shared__ uint64_t tile[(kTeRows + 1) * kTePad];
-    const long long t = xcd_block();
-    if (t >= ntiles) return;                // whole workgroup
-    const long long per_page = (long long)tiles_y * tiles_x;
-    const int page = (int)(t / per_page);
-    const int u = (int)(t - (long long)page * per_page);
-    const int tx = u / tiles_y, ty = u - tx * tiles_y;     // row tiles fastest
-    const int y0 = ty * kTeRows, j0 = tx * kTeWords;
-    const int nj = min(kTeWords, nw - j0);
-    const uint64_t *sp = src + (long long)page * spw;
-    // LDS row 0: the source row above the tile; row r + 1: source row y0 + r
-#pragma unroll
-    for (int h = 0; h < kTeRows / 256; h++) {
-        const int r = (int)threadIdx.x + 256 * h, y = y0 + r;
-        uint64_t v[kTeWords];
-        const uint64_t *q = sp + (long long)y * sstride + j0;
-        if (y < H && nj == kTeWords && (((uintptr_t)q) & 15) == 0) {
-            const ulonglong2 *q2 = reinterpret_cast<const ulonglong2 *>(q);
-#pragma unroll
-            for (int c = 0; c < kTeWords / 2; c++) {
-                const ulonglong2 w2 = q2[c];
-                v[2 * c] = w2.x;
-                v[2 * c + 1] = w2.y;
-            }
-            if (j0 + kTeWords == nw) v[kTeWords - 1] &= padmask;
-        } else {
-#pragma unroll
-            for (int c = 0; c < kTeWords; c++) v[c] = tile_word(sp, y, H, sstride, j0 + c, nw, padmask);
-        }
-#pragma unroll
-        for (int c = 0; c < kTeWords; c++) tile[(r + 1) * kTePad + c] = v[c];
-    }
-    if (threadIdx.x < kTeWords)
-        tile[threadIdx.x] = tile_word(sp, y0 - 1, H, sstride, j0 + (int)threadIdx.x, nw, padmask);
-    __syncthreads();
-    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-    const int nkk = min(kTeBlocks, (H + 63) / 64 - y0 / 64);     // row blocks of this tile
-#pragma unroll
-    for (int hc = 0; hc < kTeColsPerWave; hc++) {
-        const int jj = kTeColsPerWave * wv + hc;           // word column of the tile
-        const int x = 64 * (j0 + jj) + lane;               // transposed row within the page
-        uint64_t prev = (tile[jj] >> lane) & 1ull;         // the pixel above the piece
-        int cnt = 0;
-        for (int kk = 0; kk < kTeBlocks; kk++) {
-            if (kk >= nkk) break;                          // wave-uniform
-            const uint64_t o = wave_transpose64(tile[(1 + 64 * kk + lane) * kTePad + jj]);
-            cnt += __popcll(o & ~((o << 1) | prev));
-            prev = o >> 63;
-        }
-        if (jj < nj && x < W) piece_cnt[((long long)page * W + x) * tiles_y + ty] = cnt;
-    }
-}
-
-__global__ __launch_bounds__(256) void transposed_to_rle_kernel(
-    const uint64_t *__restrict__ src, int W, int H, int sstride, long long spw, uint64_t padmask, int nw,
-    int P, int tiles_y, const int *__restrict__ piece_off, int *__restrict__ row_ptr, int *__restrict__ runs,
-    long long cap, unsigned long long *trace)
-{
-    __shared__ uint64_t buf[64 * kTeCols * kTeRs];
-    const int ncg = (nw + kTeCols - 1) / kTeCols;
-    const long long t = xcd_block();
-    if (t >= (long long)P * ncg) return;    // whole workgroup
-    const int page = (int)(t / ncg);
-    const int j0 = (int)(t - (long long)page * ncg) * kTeCols;
-    const uint64_t *sp = src + (long long)page * spw;
-    const int nk = (H + 63) / 64;
-    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-    const int gl = glane(), grp = (int)(threadIdx.x >> 4);
-    const long long R = (long long)P * W;
-    // state of the rows this group encodes (rows grp + 16 q of the
-    // workgroup): output offset, ends so far, last start, top bit of the
-    // word before
-    long long obase[kTeRowsPerGroup];
-    int cend[kTeRowsPerGroup], lstart[kTeRowsPerGroup], prevb[kTeRowsPerGroup];
-#pragma unroll
-    for (int q = 0; q < kTeRowsPerGroup; q++) {
-        const int i = grp + kGroupsPerBlock * q, c = i >> 6;
-        const int x = 64 * (j0 + c) + (i & 63);
-        obase[q] = 0;
-        if (j0 + c < nw && x < W) {
-            const long long row = (long long)page * W + x;
-            obase[q] = piece_off[row * tiles_y];
-            if (gl == 0) {
-                row_ptr[row] = (int)obase[q];
-                if (row == R - 1) row_ptr[R] = piece_off[R * tiles_y];   // the total
-            }
-        }
-        cend[q] = 0;
-        lstart[q] = -1;
-        prevb[q] = 0;
-    }
-    unsigned long long written = 0;
-    for (int k0 = 0; k0 <= nk; k0 += kTeChunk) {          // one block past the last: a zero word
-        // the chunk's blocks, turned, row by row into LDS
-        for (int kb = wv; kb < kTeChunk; kb += 4) {        // wave-uniform
-            const int y = 64 * (k0 + kb) + lane;
-            uint64_t v[kTeCols];
-            const uint64_t *q = sp + (long long)y * sstride + j0;
-            if (y < H && j0 + kTeCols <= nw && (((uintptr_t)q) & 15) == 0) {
-                const ulonglong2 w2 = *reinterpret_cast<const ulonglong2 *>(q);
-                v[0] = w2.x;
-                v[1] = j0 + 2 == nw ? (w2.y & padmask) : w2.y;
-                if (j0 + 1 == nw) v[0] &= padmask;
-            } else {
-#pragma unroll
-                for (int c = 0; c < kTeCols; c++) v[c] = tile_word(sp, y, H, sstride, j0 + c, nw, padmask);
-            }
-#pragma unroll
-            for (int c = 0; c < kTeCols; c++) buf[(64 * c + lane) * kTeRs + kb] = wave_transpose64(v[c]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kTeRowsPerGroup; q++) {
-            const int i = grp + kGroupsPerBlock * q, c = i >> 6;
-            const int x = 64 * (j0 + c) + (i & 63);
-            if (j0 + c >= nw || x >= W) continue;          // whole group
-            const int kw = k0 + gl;                        // this lane's block of the column
-            const uint64_t a = buf[i * kTeRs + gl];
-            const int top = (int)(a >> 63);
-            const int up = __builtin_amdgcn_update_dpp(prevb[q], top, 0x111, 0xf, 0xf, false);   // row_shr:1
-            const uint64_t sh = (a << 1) | (uint64_t)(unsigned)up;
-            uint64_t st = a & ~sh, en = ~a & sh;
-            if (kw > nk) {
-                st = 0;
-                en = 0;
-            }
-            const int ne = __popcll(en);
-            const int ie = group_incl_scan(ne);
-            // every run written whole by the lane of its end, its start the
-            // nearest start below the end in the word or else the last start
-            // of an earlier word (as in the bitmap encoder)
-            const int ls = st ? 64 * kw + 63 - (int)__clzll(st) : -1;
-            const int incl = group_incl_max(ls);
-            const int before = max(lstart[q], __builtin_amdgcn_update_dpp(-1, incl, 0x111, 0xf, 0xf, false));
-            long long k = obase[q] + cend[q] + ie - ne;
-            while (en) {
-                const int b = __ffsll((unsigned long long)en) - 1;
-                const uint64_t below = st & ((1ull << b) - 1);
-                const int s0 = below ? 64 * kw + 63 - (int)__clzll(below) : before;
-                if (k < cap) reinterpret_cast<int2 *>(runs)[k] = make_int2(s0, 64 * kw + b);
-                k++;
-                en &= en - 1;
-            }
-            lstart[q] = max(lstart[q], group_last(incl));
-            cend[q] += group_last(ie);
-            prevb[q] = group_last(top);
-            written += (unsigned long long)ne;
-        }
-        __syncthreads();
-    }
-    if (trace) {
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) written += __shfl_xor(written, d, 64);
-        if (lane == 0) trace_add(trace, 0, written);
-    }
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    const int *p = pieces + r * per_row;
+    int s = 0;
+    for (int k = 0; k < per_row; k++) s += p[k];
+    counts[r] = s;
 }
 
 // The number of 16-run blocks the longest of the wave's four rows needs
@@ -1772,35 +1610,37 @@ hipError_t rle_to_packed(const morph_bitmap_t &dst, const morph_rle_t &src, hipS
 
 size_t transposed_rle_workspace(int W, int H, int P)
 {
-    const long long n = (long long)W * P * ((H + kTeRows - 1) / kTeRows);
-    return r256((size_t)n * 4) + r256((size_t)(n + 1) * 4) + r256(scan_workspace(n));
+    const long long R = (long long)W * P;
+    return r256((size_t)R * transpose_pieces(H) * 4) + r256((size_t)R * 4) + r256(scan_workspace(R));
 }
 
-hipError_t rle_from_packed_transposed(const morph_rle_t &dst, const morph_bitmap_t &src, void *ws, hipStream_t s)
+hipError_t rle_from_packed_transposed(const morph_rle_t &dst, const morph_bitmap_t &src, uint64_t *tbuf, void *ws,
+                                      hipStream_t s)
 {
     const int W = src.width, H = src.height, P = src.npages;
-    const int nw = (W + 63) / 64;
-    const int tiles_y = (H + kTeRows - 1) / kTeRows, tiles_x = (nw + kTeWords - 1) / kTeWords;
-    const long long ntiles = (long long)tiles_y * tiles_x * P;
-    const long long n = (long long)W * P * tiles_y;
-    const long long ncols = (long long)P * ((nw + kTeCols - 1) / kTeCols);
-    if (ntiles <= 0) return hipSuccess;
-    if (ntiles > 0x7fffffffLL || ncols > 0x7fffffffLL || n >= 0x7fffffffLL) return hipErrorInvalidValue;
-    const uint64_t pad = (W % 64) ? ((1ull << (W % 64)) - 1) : ~0ull;
-    int *cnt = (int *)ws;
-    int *off = (int *)((char *)ws + r256((size_t)n * 4));
-    int *tmp = (int *)((char *)off + r256((size_t)(n + 1) * 4));
-    const long long spw = (long long)src.stride_words * H;
+    const long long R = (long long)W * P;
+    const int np = transpose_pieces(H), nwt = (H + 63) / 64;
+    if (R <= 0) return hipSuccess;
+    if (R >= 0x7fffffffLL || nwt > kNarrowRowWords) return hipErrorInvalidValue;
+    int *pieces = (int *)ws;
+    int *cnt = (int *)((char *)ws + r256((size_t)R * np * 4));
+    int *tmp = (int *)((char *)cnt + r256((size_t)R * 4));
+    const morph_bitmap_t T{tbuf, H, W, nwt, P};
     unsigned long long *tr = trace_counters();
     trace_before(MORPH_K_TRANSPOSE_TO_RLE, s);
-    hipLaunchKernelGGL(transposed_count_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, src.words, W, H,
-                       src.stride_words, spw, pad, nw, tiles_y, tiles_x, ntiles, cnt);
-    hipError_t e = exclusive_scan(cnt, (int)n, off, tmp, s);
+    hipError_t e = packed_transpose_counted(T, src, pieces, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(transposed_to_rle_kernel, dim3((unsigned)ncols), dim3(256), 0, s, src.words, W, H,
-                       src.stride_words, spw, pad, nw, P, tiles_y, off, dst.row_ptr, dst.runs,
+    hipLaunchKernelGGL(piece_sum_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, s, pieces, np, R, cnt);
+    e = exclusive_scan(cnt, (int)R, dst.row_ptr, tmp, s);
+    if (e != hipSuccess) return e;
+    const uint64_t pad = (H % 64) ? ((1ull << (H % 64)) - 1) : ~0ull;
+    hipLaunchKernelGGL((pack_to_rle_group_kernel<true>), dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s,
+                       T.words, nwt, nwt, W, (int)R, (long long)nwt * W, pad, nullptr, dst.row_ptr, dst.runs,
                        (long long)dst.capacity, trace_block(tr, MORPH_K_TRANSPOSE_TO_RLE));
-    trace_after(MORPH_K_TRANSPOSE_TO_RLE, s, 8.0 * (double)nw * H * P + 4.0 * ((double)W * P + 1));
+    // algorithmic: the page read, the transpose written and read back, the
+    // row offsets (the runs written come from the run counters)
+    trace_after(MORPH_K_TRANSPOSE_TO_RLE, s,
+                8.0 * P * ((double)((W + 63) / 64) * H + 2.0 * nwt * W) + 4.0 * ((double)R + 1));
     return hipGetLastError();
 }
 

@@ -193,11 +193,12 @@ def test_trace_names_the_transpose_kernels():
         M.transpose_packed(bitmap_gpu(img))
     res = tr.result
     assert res["decode_transpose_kernel"]["launches"] == 2
-    # rows of up to 128 words are decoded in their own orientation and the
-    # runs of the transpose encoded from that bitmap: no transposed bitmap
-    # (the one bit-block transpose is the direct call)
+    # rows of up to 128 words are decoded in their own orientation, and the
+    # transpose of that bitmap comes with its rows' run counts, from which the
+    # runs are encoded: one traced conversion each way (the traced bit-block
+    # transpose is the direct call)
     assert res["transpose_kernel"]["launches"] == 1
-    assert res["transposed_to_rle_kernel"]["launches"] == 2
+    assert res["transpose_to_rle"]["launches"] == 2
     assert "pack_to_rle_kernel" not in res
     n = int(src.nruns())
     # algorithmic bytes of the first decode: the runs and row counts read,
