@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--sequential", action="store_true",
                     help="run the packed and the run-length operations of a timed step on one stream")
+    ap.add_argument("--rle-lanes", type=int, default=2, choices=(1, 2, 3),
+                    help="streams the run-length operations of a timed step are spread over")
     g = ap.add_argument_group("profile summary (no GPU): rocprofv3 CSV output -> markdown")
     g.add_argument("--summarize-profile", action="store_true")
     g.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output directory")
@@ -831,6 +833,41 @@ def main():
 
     side = torch.cuda.Stream(device=dev)       # default priority
 
+    def rle_call(op, name, se, d, w_l, w_t):
+        if strategy[(op, name)] == "transpose":
+            M.morph_rect_rlet(op, d, rle_src, se, w_t)
+        else:
+            M.RLE_OPS[op](d, rle_src, se, w_l)
+
+    # The run-length operations of a step are independent of one another
+    # (one input, results not reused): with their own output and workspaces,
+    # further lanes run part of them on streams of their own.  Each operation
+    # is timed once here and the lanes are filled longest first.
+    lanes = args.rle_lanes if (do_rle and not args.sequential) else 1
+    lane_of = {}
+    lane_bufs = [(rle_dst, ws_rle, ws_rlet)]
+    lane_streams = []
+    if do_rle and lanes > 1:
+        for _ in range(lanes - 1):
+            lane_bufs.append((M.RLE.empty(W, H, B, capacity=max_runs, device=dev),
+                              torch.empty(ws_rle_n, dtype=torch.uint8, device=dev),
+                              torch.empty(ws_rlet.numel(), dtype=torch.uint8, device=dev)
+                              if ws_rlet is not None else None))
+            lane_streams.append(torch.cuda.Stream(device=dev))     # default priority
+        est = {}
+        for op, name, se in packed_jobs:
+            rle_call(op, name, se, rle_dst, ws_rle, ws_rlet)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rle_call(op, name, se, rle_dst, ws_rle, ws_rlet)
+            torch.cuda.synchronize()
+            est[(op, name)] = time.perf_counter() - t0
+        load = [0.0] * lanes
+        for key in sorted(est, key=lambda k: -est[k]):
+            ln = min(range(lanes), key=lambda i: load[i])
+            lane_of[key] = ln
+            load[ln] += est[key]
+
     def step(ev=None, conc=False):
         # conc: the packed operations run on a second stream beside the
         # run-length chain (independent inputs and outputs), joined at the end
@@ -854,13 +891,21 @@ def main():
             M.morph_pack_to_rle(rle_src, src, ws_p2r)
             if ev is not None:
                 ev["p2r"][1].record(stream)
+            multi = conc and lanes > 1
+            if multi:
+                for ln, st in enumerate(lane_streams, start=1):
+                    st.wait_stream(cur)
+                    d, w_l, w_t = lane_bufs[ln]
+                    with torch.cuda.stream(st):
+                        for op, name, se in packed_jobs:
+                            if lane_of[(op, name)] == ln:
+                                rle_call(op, name, se, d, w_l, w_t)
             for k, (op, name, se) in enumerate(packed_jobs):
+                if multi and lane_of[(op, name)] != 0:
+                    continue
                 if ev is not None:
                     ev["rle"][k][0].record(stream)
-                if strategy[(op, name)] == "transpose":
-                    M.morph_rect_rlet(op, rle_dst, rle_src, se, ws_rlet)
-                else:
-                    M.RLE_OPS[op](rle_dst, rle_src, se, ws_rle)
+                rle_call(op, name, se, rle_dst, ws_rle, ws_rlet)
                 if ev is not None:
                     ev["rle"][k][1].record(stream)
             if ev is not None:
@@ -868,6 +913,9 @@ def main():
             M.morph_rle_to_pack(back, rle_dst)
             if ev is not None:
                 ev["r2p"][1].record(stream)
+            if multi:
+                for st in lane_streams:
+                    cur.wait_stream(st)
         if conc:
             cur.wait_stream(side)
 
@@ -890,7 +938,8 @@ def main():
     # point allocates, synchronises or records a memset); its outputs must
     # equal the eager step's byte for byte
     graph_check = {}
-    outs = lambda: (dst.words, back.words, rle_src.row_ptr, rle_src.runs, rle_dst.row_ptr, rle_dst.runs)
+    outs = lambda: (dst.words, back.words, rle_src.row_ptr, rle_src.runs) + tuple(
+        t for d, _, _ in lane_bufs for t in (d.row_ptr, d.runs))
     eager_out = [t.clone() for t in outs()]
     g_step = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g_step):
@@ -955,6 +1004,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "ms_per_step_graph": dt_graph * 1e3 / args.steps, "graph_outputs_identical": graph_check["identical"],
         "paths_on_two_streams": conc and do_packed and do_rle,
+        "rle_lanes": lanes if (conc and do_packed and do_rle) else 1,
         "ms_per_step_one_stream": dt_seq * 1e3 / args.steps if dt_seq is not None else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+i32",
         "data": "synthetic (seeded letter pages, %d distinct, resident in HBM)" % args.distinct,
