@@ -131,6 +131,9 @@ __device__ __forceinline__ void load_group(const uint64_t *row, int c0, uint64_t
 // the thread's own run of CM rows come from registers, the others from LDS,
 // where every thread first publishes the K rows its upper neighbour needs.
 // Rows at or past `rows` (the rows the tile allocates in LDS) read as 1.
+// The LDS partners are read by every lane at a row clamped into the tile and
+// then selected: behind a per-lane branch the compiler copied the whole
+// register run on every edge of it.
 template <int K>
 __device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int TWp, int rows,
                                          int col, int a, bool active)
@@ -141,18 +144,17 @@ __device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int
         for (int i = 0; i < K; i++) lds[(a + i) * TWp + col] = reg[i];
     }
     lds_barrier();
-    if (active) {
 #pragma unroll
-        for (int i = 0; i < CM; i++) {
-            uint64_t p;
-            if (i + K < CM) {
-                p = reg[(i + K < CM) ? i + K : CM - 1];
-            } else {
-                const int rr = a + i + K;
-                p = rr < rows ? lds[rr * TWp + col] : kOnes;
-            }
-            reg[i] &= p;
+    for (int i = 0; i < CM; i++) {
+        uint64_t p;
+        if (i + K < CM) {
+            p = reg[(i + K < CM) ? i + K : CM - 1];
+        } else {
+            const int rr = a + i + K;
+            const uint64_t v = lds[min(rr, rows - 1) * TWp + col];
+            p = rr < rows ? v : kOnes;
         }
+        reg[i] &= p;
     }
 }
 
@@ -166,12 +168,11 @@ __device__ __forceinline__ void col_step_lds(uint64_t *lds, uint64_t (&reg)[CM],
         for (int i = 0; i < CM; i++) lds[(a + i) * TWp + col] = reg[i];
     }
     lds_barrier();
-    if (active) {
 #pragma unroll
-        for (int i = 0; i < CM; i++) {
-            const int rr = a + i + K;
-            reg[i] &= rr < rows ? lds[rr * TWp + col] : kOnes;
-        }
+    for (int i = 0; i < CM; i++) {
+        const int rr = a + i + K;
+        const uint64_t v = lds[min(rr, rows - 1) * TWp + col];
+        reg[i] &= rr < rows ? v : kOnes;
     }
 }
 
@@ -279,7 +280,10 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
             take_loads(P, T, reg);
         } else {
 #pragma unroll
-            for (int i = 0; i < CM; i++) reg[i] = active ? lds[(a + i) * TWp + col] : kOnes;
+            for (int i = 0; i < CM; i++) {
+                const uint64_t v = lds[min(a + i, rows - 1) * TWp + col];
+                reg[i] = active ? v : kOnes;
+            }
         }
         const int h = S.h;
         int m = 1;
