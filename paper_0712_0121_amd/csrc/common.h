@@ -147,8 +147,9 @@ hipError_t popcount_pages(const morph_bitmap_t &src, unsigned long long *counts,
 // height = src width).
 hipError_t packed_transpose(const morph_bitmap_t &dst, const morph_bitmap_t &src, hipStream_t stream);
 // The same (untraced), also writing the number of runs that start in each
-// piece of every transposed row: counts[row * transpose_pieces(src height)
-// + piece], the pieces of a row being consecutive ranges of its pixels.
+// piece of every transposed row: counts[piece * rows + row] for the
+// transpose_pieces(src height) pieces of a row, consecutive ranges of its
+// pixels.
 int transpose_pieces(int height);
 hipError_t packed_transpose_counted(const morph_bitmap_t &dst, const morph_bitmap_t &src, int *counts,
                                     hipStream_t stream);

@@ -539,8 +539,8 @@ int cached_cu_count = 0;
 // With counts, each lane also counts the runs that start in its words of
 // the transposed row (the pixel before them is bit i of the source row above
 // the tile) and writes the count of its piece of the row to
-// counts[row * tiles_y + tile row]: the run counts of the transpose come
-// with the transpose itself.
+// counts[tile row * rows + row] (a wave's 64 counts contiguous): the run
+// counts of the transpose come with the transpose itself.
 constexpr int kTrRows = 512, kTrWords = 8, kTrPad = kTrWords + 1;
 constexpr int kTrRowsPerThread = kTrRows / 256, kTrColsPerWave = kTrWords / 4, kTrBlocks = kTrRows / 64;
 
@@ -611,6 +611,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(
     const long long t = xcd_block();
     if (t >= ntiles) return;                // whole workgroup
     const bool cnt_on = counts != nullptr;
+    const long long R = (long long)(ntiles / ((long long)tiles_y * tiles_x)) * W;   // transposed rows
     const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
     const TrTile C = tr_tile(t, tiles_y, tiles_x, nw);
     uint64_t v[kTrRowsPerThread][kTrWords];
@@ -638,7 +639,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(
                 cnt += __popcll(o[kk] & ~((o[kk] << 1) | prev));
                 prev = o[kk] >> 63;
             }
-            if (jj < C.nj && x < W) counts[((long long)C.page * W + x) * tiles_y + C.ty] = cnt;
+            if (jj < C.nj && x < W) counts[(long long)C.ty * R + (long long)C.page * W + x] = cnt;
         }
         if (jj < C.nj && x < W) {
             uint64_t *dp = dst + (long long)C.page * dpw + (long long)x * dstride + C.y0 / 64;

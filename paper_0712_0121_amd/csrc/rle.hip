@@ -578,9 +578,8 @@ __global__ __launch_bounds__(256) void piece_sum_kernel(const int *__restrict__ 
 {
     const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
     if (r >= R) return;
-    const int *p = pieces + r * per_row;
     int s = 0;
-    for (int k = 0; k < per_row; k++) s += p[k];
+    for (int k = 0; k < per_row; k++) s += pieces[k * R + r];    // piece-major
     counts[r] = s;
 }
 
