@@ -107,12 +107,23 @@ class Tuner:
         v = self.table["shape"].get(shape_key(W, H, op, se))
         return tuple(v["best"]) if v else (0, 0)
 
+    # The transposition route moves several bitmap-sized passes per operation
+    # where the between-line route moves runs: timed alone it may win by a
+    # hair and still cost more when operations share the device.  It is taken
+    # only when it is faster by this factor (on the letter batch a near tie
+    # taken the other way cost 1 ms of a 15 ms step run on three streams).
+    STRATEGY_MARGIN = 1.1
+
     def choose_strategy(self, op, se):
         """'lines' (within-line passes, then between-line intersections) or
         'transpose' (within-line passes along the rows and, after a
         transposition, along the columns) for an operation on runs."""
         v = self.table.get("strategy", {}).get(strategy_key(op, se))
-        return v["best"] if v else "lines"
+        if not v:
+            return "lines"
+        if "lines_ms" in v and "transpose_ms" in v:
+            return "transpose" if v["transpose_ms"] * self.STRATEGY_MARGIN < v["lines_ms"] else "lines"
+        return v["best"]
 
     def choose_repr(self, density, op, se):
         """'packed' or 'rle' for a page held packed, conversions included."""
@@ -245,7 +256,8 @@ class Tuner:
             a, b = per_key.get(k, (0.0, 0.0))
             per_key[k] = (a + t_l, b + t_t)
         for k, (t_l, t_t) in per_key.items():
-            self.table.setdefault("strategy", {})[k] = {"best": "lines" if t_l <= t_t else "transpose",
+            self.table.setdefault("strategy", {})[k] = {"best": "transpose" if t_t * self.STRATEGY_MARGIN < t_l
+                                                        else "lines",
                                                         "lines_ms": t_l, "transpose_ms": t_t, "pages": P}
             if verbose:
                 print("strategy", k, self.table["strategy"][k])

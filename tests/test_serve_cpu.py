@@ -177,3 +177,15 @@ def test_strategy_lookup_defaults_to_lines(tmp_path):
     assert t.choose_strategy("close", (1, 25, 0, 12)) == "transpose"     # same width and height buckets
     assert t.choose_strategy("close", (31, 1, 15, 0)) == "lines"
     assert t.choose_strategy("open", (1, 31, 0, 15)) == "lines"
+
+
+def test_strategy_takes_transposition_only_by_a_margin(tmp_path):
+    """Timed alone, the transposition route must beat the between-line route
+    by the tuner's margin before it is chosen: near ties stay on runs."""
+    from paper_0712_0121_amd.tune import Tuner, strategy_key
+    t = Tuner(cache_path=str(tmp_path / "t.json"))
+    k = strategy_key("dilate", (21, 21, 10, 10))
+    t.table["strategy"] = {k: {"best": "transpose", "lines_ms": 1.00, "transpose_ms": 0.95}}
+    assert t.choose_strategy("dilate", (21, 21, 10, 10)) == "lines"
+    t.table["strategy"][k]["transpose_ms"] = 1.00 / t.STRATEGY_MARGIN - 0.01
+    assert t.choose_strategy("dilate", (21, 21, 10, 10)) == "transpose"
