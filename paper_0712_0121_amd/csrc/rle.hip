@@ -601,8 +601,13 @@ __device__ __forceinline__ int wave_blocks(int n)
 // that vanish are dropped.  With comp_in the rows' complements are eroded:
 // the gaps between runs, including the ones at both ends, play the runs.
 // One group of 16 lanes per row, lanes over runs, compaction by ballot.
+// With keep_whole the candidates that survive the erosion are written as
+// they were: the opening by a one-row element (section "Within-Line
+// Morphological Operations": a run survives erosion and dilation unchanged
+// when it is at least as long as the element, the border runs by their
+// shrunk length), and on the gaps, the closing's complement.
 __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W, int w, int cx, int comp_in,
-                                                        int *__restrict__ out_cnt,
+                                                        int keep_whole, int *__restrict__ out_cnt,
                                                         int *__restrict__ out_runs, long long cap_row,
                                                         unsigned long long *trace)
 {
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(256) void row_erode_kernel(RowsIn in, int R, int W,
         const bool keep = k < ncand && s < e && ns < ne;
         const unsigned gm = group_ballot(keep);
         const int idx = carry + __popc(gm & ((1u << gl) - 1));
-        if (keep && idx < cap_row) ((int2 *)o)[idx] = make_int2(ns, ne);
+        if (keep && idx < cap_row) ((int2 *)o)[idx] = keep_whole ? make_int2(s, e) : make_int2(ns, ne);
         carry += __popc(gm);
     };
     if (ncand <= kStageRuns) {
@@ -1759,7 +1764,7 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
     if (h == 1) {
         trace_before(MORPH_K_ROW_ERODE, s);
         hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
-                           cx, comp_in, L.cnt[to], L.runs[to], (long long)L.cap_row,
+                           cx, comp_in, 0, L.cnt[to], L.runs[to], (long long)L.cap_row,
                            trace_block(tr, MORPH_K_ROW_ERODE));
         trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
         *err = hipGetLastError();
@@ -1862,6 +1867,21 @@ hipError_t rle_rect_op(int op, const morph_rle_t &dst, const morph_rle_t &src, m
     // column leaves the rows as they are; there the doubling steps are
     // faster (measured on the letter batch).
     const bool wide = w > 1;
+    if (h == 1 && (op == MORPH_OPEN || op == MORPH_CLOSE)) {
+        // one row: the opening keeps the runs whose erosion is not empty,
+        // unchanged, in one pass; the closing does the same to the gaps with
+        // the reflected origin and takes the complement
+        const int comp = op == MORPH_CLOSE ? 1 : 0;
+        const int R = P * H;
+        unsigned long long *tr = trace_counters();
+        trace_before(MORPH_K_ROW_ERODE, s);
+        hipLaunchKernelGGL(row_erode_kernel, dim3(blocks_for(R, kGroupsPerBlock)), dim3(256), 0, s, in, R, W, w,
+                           comp ? rx : cx, comp, 1, L.cnt[0], L.runs[0], (long long)L.cap_row,
+                           trace_block(tr, MORPH_K_ROW_ERODE));
+        trace_after(MORPH_K_ROW_ERODE, s, 8.0 * R);
+        e = hipGetLastError();
+        return e != hipSuccess ? e : finish(L, 0, comp, dst, W, s, false);
+    }
     switch (op) {
     case MORPH_ERODE:
         b = erode_chain(in, 0, P, W, H, w, h, cx, cy, L, 0, s, &e, nullptr, nullptr, wide);

@@ -147,6 +147,29 @@ def test_rle_fuzz(case, form):
     assert_rle_equal(rle_op(op, img, se, form=form), oracle.sat_apply(op, img, se), str(case))
 
 
+def row_fuzz(n, seed):
+    # one-row elements, every origin, widths from 1 to past the row: the
+    # opening and closing take their one-pass form there
+    r = np.random.default_rng(seed)
+    for i in range(n):
+        W = int(r.choice([1, 3, 63, 64, 65, 130, int(r.integers(1, 400))]))
+        H = int(r.integers(1, 40))
+        w = int(r.choice([1, 2, 3, int(r.integers(1, 40)), W, W + 3]))
+        yield i, W, H, (w, 1, int(r.integers(w)), 0), ("open", "close")[i % 2]
+
+
+@pytest.mark.parametrize("case", list(row_fuzz(40, 11)), ids=lambda c: "c%d" % c[0])
+def test_rle_one_row_open_close(case):
+    """Opening and closing by a one-row element (one pass: runs, or gaps,
+    kept whole when their erosion is not empty) against the oracle's
+    dilation of the erosion, border runs and gaps included."""
+    i, W, H, se, op = case
+    r = np.random.default_rng(900 + i)
+    img = (r.random((H, W)) < r.uniform(0.2, 0.8)).astype(np.uint8)
+    img[:, :1] = r.integers(0, 2, (H, 1))         # runs and gaps on both borders
+    assert_rle_equal(rle_op(op, img, se), oracle.apply(op, img, se), str(case))
+
+
 @pytest.mark.parametrize("density", [0.01, 0.10, 0.40])
 @pytest.mark.parametrize("op", ["erode", "dilate"])
 @pytest.mark.parametrize("se", [(41, 1, 20, 0), (1, 41, 0, 20)], ids=["1x41", "41x1"])
