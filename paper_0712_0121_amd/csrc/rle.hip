@@ -878,8 +878,28 @@ __device__ __forceinline__ void shrink_regs(const RowX &x, int2 (&v)[kARegs], in
 // stored row x - off if that lies in [0, real), and otherwise a full row
 // [0, W) (outside the image erosion sees 1s).  NA rows per page come in,
 // NA - K go out.  One group of lanes per output row.
+// n / d for 0 <= n < 2^31 as a multiply-high, an add and a shift, with
+// the round-up multiplier m = floor(2^32 (2^l - d) / d) + 1, l = ceil(log2 d)
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication"): the wave-uniform divisor's quotient costs three VALU
+// instructions instead of a reciprocal sequence.
+struct DivU {
+    unsigned mul;
+    int shift;
+};
+
+static DivU div_by(unsigned d)
+{
+    int l = 0;
+    while ((1ull << l) < d) l++;
+    const unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return DivU{(unsigned)m, l};
+}
+
+__device__ __forceinline__ unsigned div_u(unsigned n, DivU q) { return (__umulhi(n, q.mul) + n) >> q.shift; }
+
 template <bool ROWX>
-__global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, int P,
+__global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int real, int NA, int K, DivU nbd, int P,
                                                       int W, RowX x, int *__restrict__ out_cnt,
                                                       int *__restrict__ out_runs, long long cap_row,
                                                       int *__restrict__ gap_cnt, unsigned long long *trace)
@@ -894,7 +914,7 @@ __global__ __launch_bounds__(256) void col_and_kernel(RowsIn in, int off, int re
     const int gl = glane();
     // the host keeps every row index below 2^31: 32-bit division
     const unsigned tu = (unsigned)t;
-    const int page = (int)(tu / (unsigned)NB), r = (int)(tu - (unsigned)page * (unsigned)NB);
+    const int page = (int)div_u(tu, nbd), r = (int)(tu - (unsigned)page * (unsigned)NB);
     const int ia = r - off, ib = r + K - off;
     const bool va = ia >= 0 && ia < real, vb = ib >= 0 && ib < real;
     int *o = out_runs + 2 * t * cap_row;
@@ -1781,7 +1801,8 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
         const int fin = 1 - to;
         trace_before(MORPH_K_COL_AND, s);
         hipLaunchKernelGGL(col_and_kernel<false>, dim3(blocks_for((long long)P * H, kGroupsPerBlock)), dim3(256), 0, s,
-                           slot_rows(L, to), 0, 2 * NA, 2 * NA, NA + h - 1, P, W, xs, L.cnt[fin], L.runs[fin],
+                           slot_rows(L, to), 0, 2 * NA, 2 * NA, NA + h - 1, div_by((unsigned)(NA - h + 1)), P, W, xs,
+                           L.cnt[fin], L.runs[fin],
                            (long long)L.cap_row, gap_out, trace_block(tr, MORPH_K_COL_AND));
         trace_after(MORPH_K_COL_AND, s, 4.0 * P * (2.0 * NA + H));
         if (gap_out && gaps_done) *gaps_done = true;
@@ -1803,12 +1824,13 @@ static int erode_chain(const RowsIn &in, int comp_in, int P, int W, int H, int w
         int *gaps = (k == n - 1) ? gap_out : nullptr;   // the last step counts the complement's runs
         trace_before(MORPH_K_COL_AND, s);
         if (cur < 0)
-            hipLaunchKernelGGL(col_and_kernel<true>, grid, dim3(256), 0, s, in, off, real, NA, K, P, W, x,
+            hipLaunchKernelGGL(col_and_kernel<true>, grid, dim3(256), 0, s, in, off, real, NA, K, div_by((unsigned)NB),
+                               P, W, x,
                                L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, gaps,
                                trace_block(tr, MORPH_K_COL_AND));
         else
             hipLaunchKernelGGL(col_and_kernel<false>, grid, dim3(256), 0, s, slot_rows(L, cur), off, real, NA, K,
-                               P, W, x, L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, gaps,
+                               div_by((unsigned)NB), P, W, x, L.cnt[nxt], L.runs[nxt], (long long)L.cap_row, gaps,
                                trace_block(tr, MORPH_K_COL_AND));
         if (gaps && gaps_done) *gaps_done = true;
         trace_after(MORPH_K_COL_AND, s, 4.0 * P * ((double)real + NB));
