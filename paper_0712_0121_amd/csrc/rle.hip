@@ -584,14 +584,15 @@ __global__ __launch_bounds__(256) void piece_sum_kernel(const int *__restrict__ 
 }
 
 // The number of 16-run blocks the longest of the wave's four rows needs
-// (n runs each), read from one lane of each group: loops over register
-// blocks end on a uniform branch.  Groups that left early leave stale
-// values in their lanes, which can only raise the bound.
+// (n <= kStageRuns runs each), read from one lane of each group: loops over
+// register blocks end on a uniform branch.  Groups that left early leave
+// stale values in their lanes: compared unsigned and clamped, they can only
+// raise the bound, to at most the blocks of kStageRuns runs.
 __device__ __forceinline__ int wave_blocks(int n)
 {
-    const int m = max(max(__builtin_amdgcn_readlane(n, 0), __builtin_amdgcn_readlane(n, 16)),
-                      max(__builtin_amdgcn_readlane(n, 32), __builtin_amdgcn_readlane(n, 48)));
-    return (m + kGroup - 1) / kGroup;
+    const unsigned m = max(max((unsigned)__builtin_amdgcn_readlane(n, 0), (unsigned)__builtin_amdgcn_readlane(n, 16)),
+                           max((unsigned)__builtin_amdgcn_readlane(n, 32), (unsigned)__builtin_amdgcn_readlane(n, 48)));
+    return (int)((min(m, (unsigned)kStageRuns) + kGroup - 1) / kGroup);
 }
 
 // ------------------------------------------------------ within-line pass
