@@ -75,7 +75,7 @@ struct Launch {
 // 512-thread ones (measured a few percent faster for short elements; the
 // number of launches does not change).  With by_halo (single operations and
 // their workspace query, not batch pages, which need one launch each), two
-// stages whose halo rows outnumber a fused tile's rows run as two launches.
+// stages whose halo rows pass 0.6 of a fused tile's rows run as two launches.
 static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int tile_rows,
                           int strip_words, std::vector<Launch> &out, bool small_tiles = false,
                           bool by_halo = false)
@@ -104,16 +104,17 @@ static bool plan_launches(int op, morph_se_t se, int W, int H, int npages, int t
                 // workspace query sees a stack's total rows, the operation
                 // one page's.  r.TR is the most output rows a fused tile
                 // can hold.  With by_halo, the stages share a tile only
-                // while their halo rows (h1 - 1 + h2 - 1) do not outnumber
+                // while their halo rows (h1 - 1 + h2 - 1) stay within 0.6 of
                 // those: beyond that the first stage recomputes more rows
                 // than two single-stage launches cost with the
-                // intermediate's round trip through HBM (51 x 51 opening of
-                // letter pages: fused tiles of 76 rows under 100 halo rows,
-                // 0.57 ms; two launches 0.41 ms)
+                // intermediate's round trip through HBM.  Letter pages:
+                // opening by 51 x 51, 100 halo rows over fused tiles of 120
+                // rows, 0.42 ms fused and 0.35 ms as two launches; by 31 x 1,
+                // 60 over 160, 0.23 ms fused and 0.28 ms as two launches.
                 RectPage r = p;
                 r.H = 1 << 30;
                 share = plan_tiles(r, 1 << 30, strip_words, npages) && r.TR >= 8 &&
-                        (!by_halo || ps[i].st.h - 1 + ps[i + 1].st.h - 1 <= r.TR);
+                        (!by_halo || 5 * (ps[i].st.h - 1 + ps[i + 1].st.h - 1) <= 3 * r.TR);
             }
             if (share) {
                 p = q;

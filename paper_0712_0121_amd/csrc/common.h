@@ -94,7 +94,7 @@ constexpr int kThreadsSmall = 256;     // threads per workgroup (small tiles: fo
 constexpr int kLdsWordsSmall = 5116;   // ~40 KiB of LDS per small-tile workgroup
 
 constexpr int lds_words_for(int nt) { return nt == kThreadsSmall ? kLdsWordsSmall : kLdsWords; }
-constexpr int kChunkMax = 16;          // rows a thread keeps in registers in the column pass
+constexpr int kChunkMax = 20;          // rows a thread keeps in registers in the column pass
 constexpr int kWordsPerItem = 4;       // consecutive words one row-pass item produces
 constexpr int kItemsMax = 4;           // row-pass items a thread holds across a barrier
 constexpr int kReachMax = 64;          // pixels each side of the origin one pass can reach (row)

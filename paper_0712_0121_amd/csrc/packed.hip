@@ -130,10 +130,13 @@ __device__ __forceinline__ void load_group(const uint64_t *row, int c0, uint64_t
 // Column doubling step with a compile-time offset K < CM: partners inside
 // the thread's own run of CM rows come from registers, the others from LDS,
 // where every thread first publishes the K rows its upper neighbour needs.
-// Rows at or past `rows` (the rows the tile allocates in LDS) read as 1.
-// The LDS partners are read by every lane at a row clamped into the tile and
-// then selected: behind a per-lane branch the compiler copied the whole
-// register run on every edge of it.
+// A stage of h rows keeps only the output rows whose window of h rows lies
+// below its input rows, and every partner of such a row (at most h - 1
+// rows below it) lies there too.  Partner rows at or past `rows` (the rows
+// the tile allocates in LDS) therefore feed only rows that are dropped:
+// they are read at the last allocated row, which keeps the access in bounds
+// without a select.  The partner's word index advances by the pitch, with
+// no multiply per row.
 template <int K>
 __device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int TWp, int rows,
                                          int col, int a, bool active)
@@ -144,15 +147,16 @@ __device__ __forceinline__ void col_step(uint64_t *lds, uint64_t (&reg)[CM], int
         for (int i = 0; i < K; i++) lds[(a + i) * TWp + col] = reg[i];
     }
     lds_barrier();
+    const int last = (rows - 1) * TWp + col;
+    int idx = (a + CM) * TWp + col;         // partner of row CM - K: row a + CM
 #pragma unroll
     for (int i = 0; i < CM; i++) {
         uint64_t p;
         if (i + K < CM) {
             p = reg[(i + K < CM) ? i + K : CM - 1];
         } else {
-            const int rr = a + i + K;
-            const uint64_t v = lds[min(rr, rows - 1) * TWp + col];
-            p = rr < rows ? v : kOnes;
+            p = lds[min(idx, last)];
+            idx += TWp;
         }
         reg[i] &= p;
     }
@@ -168,11 +172,12 @@ __device__ __forceinline__ void col_step_lds(uint64_t *lds, uint64_t (&reg)[CM],
         for (int i = 0; i < CM; i++) lds[(a + i) * TWp + col] = reg[i];
     }
     lds_barrier();
+    const int last = (rows - 1) * TWp + col;
+    int idx = (a + K) * TWp + col;
 #pragma unroll
     for (int i = 0; i < CM; i++) {
-        const int rr = a + i + K;
-        const uint64_t v = lds[min(rr, rows - 1) * TWp + col];
-        reg[i] &= rr < rows ? v : kOnes;
+        reg[i] &= lds[min(idx, last)];
+        idx += TWp;
     }
 }
 
@@ -279,10 +284,13 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
         if (s == 0) {
             take_loads(P, T, reg);
         } else {
+            // inactive threads read the last row; their runs are never stored
+            const int last = (rows - 1) * TWp + col;
+            int idx = a * TWp + col;
 #pragma unroll
             for (int i = 0; i < CM; i++) {
-                const uint64_t v = lds[min(a + i, rows - 1) * TWp + col];
-                reg[i] = active ? v : kOnes;
+                reg[i] = lds[min(idx, last)];
+                idx += TWp;
             }
         }
         const int h = S.h;
