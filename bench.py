@@ -66,6 +66,12 @@ def parse():
     g.add_argument("--title", default="Kernel time and HBM traffic: letter-page workload, 256 pages")
     g.add_argument("--cmd", action="append", help="profiling command to list in the summary")
     g.add_argument("--out", help="markdown file to write")
+    g.add_argument("--summarize-sq", action="store_true",
+                   help="SQ counters per kernel (and per packed case with --cases packed) from one --pmc run "
+                        "and one --kernel-trace run of the same command")
+    g.add_argument("--sq-dir", help="rocprofv3 --pmc output directory with SQ_* counters")
+    g.add_argument("--cases", choices=["none", "packed"], default="none",
+                   help="also list the last step's packed letter cases, one row per launch")
     return ap.parse_args()
 
 
@@ -308,6 +314,79 @@ def summarize_profile(args):
         if k in traffic:
             h = hashlib.sha256(open(os.path.join(root, src), "rb").read()).hexdigest()[:16]
             lines.append("traffic %s bytes_per_launch=%.0f source=%s sha256_16=%s" % (k, traffic[k], src, h))
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", args.out)
+
+
+VALU_ISSUE_PER_S = 256 * 2.4e9      # CU-cycles per second (256 CUs at 2.4 GHz)
+
+
+def summarize_sq(args):
+    """Writes the markdown SQ-counter summary: per library kernel, the SQ
+    counters of the --pmc run summed over its dispatches and divided by its
+    waves, with the average duration from the --kernel-trace run of the same
+    command and the VALU instructions per CU-cycle of that time.
+    With --cases packed, also one row per launch of the last step's packed
+    letter cases (the last rect_kernel dispatches of both runs, in order)."""
+    pmc = _csv_rows(args.sq_dir, "_counter_collection.csv")
+    trace = sorted(_csv_rows(args.trace_dir, "_kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    disp = {}
+    for r in pmc:
+        e = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    counters = sorted({r["Counter_Name"] for r in pmc if r["Counter_Name"].startswith("SQ_")} - {"SQ_WAVES"})
+    dur = {}
+    for r in trace:
+        dur.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["# %s" % args.title, "", "Commands (from the repository root, on one MI355X):", "", "```",
+             "export TMPDIR=/tmp"] + list(args.cmd or []) + [
+             "python3 bench.py --summarize-sq --sq-dir %s --trace-dir %s --cases %s --out %s"
+             % (args.sq_dir, args.trace_dir, args.cases, args.out), "```", "",
+             "Per kernel: counters summed over its dispatches and divided by its waves; average duration from "
+             "the kernel trace. VALU / CU-cycle = VALU instructions per dispatch / (256 CUs x 2.4 GHz x "
+             "duration): 1.0 would be one wave64 VALU instruction per CU per cycle. It is an index of how much "
+             "of a kernel's time its VALU instructions account for, not a bound: a kernel here reaches more "
+             "than 1.0, so part of the mix issues faster than that.", ""]
+    head = "| kernel | dispatches | waves / dispatch | " + " | ".join(
+        c.replace("SQ_", "").replace("INSTS_", "") + " / wave" for c in counters) + " | average us | VALU / CU-cycle |"
+    lines += [head, "|" + "---|" * (len(counters) + 5)]
+    groups = {}
+    for e in disp.values():
+        if "morph::" in e["name"]:          # the library's kernels, not torch's helpers
+            groups.setdefault(e["name"], []).append(e)
+    for name, es in sorted(groups.items(), key=lambda kv: -sum(x.get("SQ_INSTS_VALU", 0.0) for x in kv[1])):
+        waves = sum(x.get("SQ_WAVES", 0.0) for x in es)
+        if waves <= 0 or name not in dur:
+            continue
+        us = sum(dur[name]) / len(dur[name])
+        valu = sum(x.get("SQ_INSTS_VALU", 0.0) for x in es) / len(es)
+        cells = ["%.1f" % (sum(x.get(c, 0.0) for x in es) / waves) for c in counters]
+        lines.append("| %s | %d | %.0f | %s | %.1f | %.2f |" % (
+            short_kernel_name(name).replace("anon::", "") + ("<%s>" % name.split("<")[1].split(">")[0]
+                                                              if "<" in name else ""),
+            len(es), waves / len(es), " | ".join(cells), us, valu / VALU_ISSUE_PER_S / (us * 1e-6)))
+    if args.cases == "packed":
+        import paper_0712_0121_amd as M
+        labels = []
+        for name, se in LETTER_SES:
+            for op in OPS:
+                split = M.morph_workspace_bytes(op, M.MORPH_PACKED, LETTER_W, LETTER_H * args.pages, se) > 0
+                labels += ["%s %s (%d/2)" % (op, name, i + 1) for i in range(2)] if split else ["%s %s" % (op, name)]
+        rk = [k for k in sorted(disp) if "rect_kernel" in disp[k]["name"]][-len(labels):]
+        rt = [r for r in trace if "rect_kernel" in r["Kernel_Name"]][-len(labels):]
+        lines += ["", "The last step's packed letter cases, one row per launch:", "",
+                  "| case | threads | us | VALU / wave | SALU / wave | LDS / wave | LDS bank conflict / wave "
+                  "| VALU / CU-cycle |", "|---|---|---|---|---|---|---|---|"]
+        for lab, k, t in zip(labels, rk, rt):
+            e = disp[k]
+            w = e.get("SQ_WAVES", 1.0)
+            us = (int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e3
+            lines.append("| %s | %s | %.1f | %.0f | %.0f | %.0f | %.0f | %.2f |" % (
+                lab, t["Kernel_Name"].split("<")[1].split(">")[0], us, e.get("SQ_INSTS_VALU", 0.0) / w,
+                e.get("SQ_INSTS_SALU", 0.0) / w, e.get("SQ_INSTS_LDS", 0.0) / w,
+                e.get("SQ_LDS_BANK_CONFLICT", 0.0) / w,
+                e.get("SQ_INSTS_VALU", 0.0) / VALU_ISSUE_PER_S / (us * 1e-6)))
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", args.out)
@@ -771,6 +850,9 @@ def main():
     args = parse()
     if args.summarize_profile:
         summarize_profile(args)
+        return
+    if args.summarize_sq:
+        summarize_sq(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (run --gpus 1)" % args.gpus,
