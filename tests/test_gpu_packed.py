@@ -192,3 +192,15 @@ def test_repeatable_and_tiling_independent(letter):
     a = run_packed("open", letter, se)
     for _ in range(3):
         np.testing.assert_array_equal(run_packed("open", letter, se), a)
+
+
+@pytest.mark.parametrize("H", [199, 220, 221, 232, 240, 241, 461])
+def test_tile_row_boundaries(H):
+    """Letter-width pages whose heights fall just under, on and over the
+    rows of one tile (220 output rows for a two-stage 3 x 3 tile, 240 for
+    a one-stage one, halo rows included or not): every band edge and the
+    last, shorter band meet the oracle."""
+    img = blobs_img(8000 + H, H, 2550, 0.3)
+    for op in pagegen.OPS:
+        for se in [(3, 3, 1, 1), (21, 21, 10, 10), (1, 31, 0, 15), (51, 51, 25, 25)]:
+            check(op, img, se, method="sat")
