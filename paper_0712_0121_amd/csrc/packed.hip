@@ -183,6 +183,16 @@ __device__ __forceinline__ void col_step_lds(uint64_t *lds, uint64_t (&reg)[CM],
 
 // Geometry of one tile: TR output rows x SW words of one page, plus the rows
 // and words it depends on.
+// LDS pitch (words) of a tile row TW words wide: even, for the 16-byte row
+// reads of the row pass, and for two stages 2 mod 4, so that the first
+// stage's write-back of 4-word groups (whose starts lie 32 bytes apart within
+// a row) spreads over twice as many banks across rows.
+__host__ __device__ __forceinline__ int tile_pitch(int TW, int nst)
+{
+    const int p = TW + (TW & 1);
+    return (nst == 2 && (p & 3) == 0) ? p + 2 : p;
+}
+
 struct Tile {
     const uint64_t *src;
     uint64_t *dst;
@@ -202,7 +212,7 @@ __device__ __forceinline__ Tile make_tile(const RectPage &P, int page, int band,
     T.j0 = strip * P.SW;
     T.SWv = min(P.SW, P.nw - T.j0);
     T.TW = T.SWv + 2 * P.nst;
-    T.TWp = T.TW + (T.TW & 1);
+    T.TWp = tile_pitch(T.TW, P.nst);
     int hsum = P.st[0].h - 1, top = P.st[0].cy;
     if (P.nst == 2) { hsum += P.st[1].h - 1; top += P.st[1].cy; }
     T.NR = T.TRv + hsum;
@@ -832,13 +842,13 @@ int device_cu_count()
 
 // Largest number of rows (input rows of the first stage) a tile of width TW
 // can hold for page p, or 0 if none: the LDS array (rows are allocated in
-// runs of kChunkMax, pitch rounded up to even, 8 words of slack), the
+// runs of kChunkMax at the pitch of tile_pitch, 8 words of slack), the
 // column runs (one thread per run, so runs per column <= threads / columns),
 // and the row-pass results a thread holds across a barrier in every stage
 // but the last.
 static int max_rows(const RectPage &p, int TW)
 {
-    const int TWp = TW + (TW & 1);
+    const int TWp = tile_pitch(TW, p.nst);
     const int nthreads = p.nt;
     int nr = ((lds_words_for(p.nt) - 8) / TWp) / kChunkMax * kChunkMax;
     int drop = 0;                   // rows consumed before stage s
@@ -921,7 +931,7 @@ bool tile_fits(const RectPage &p)
         hsum += S.h - 1;
     }
     const int TW = p.SW + 2 * p.nst;
-    const int TWp = TW + (TW & 1);
+    const int TWp = tile_pitch(TW, p.nst);
     int NRs = p.TR + hsum;
     const int rows0 = (NRs + kChunkMax - 1) / kChunkMax * kChunkMax;
     if ((long long)rows0 * TWp + 8 > lds_words_for(p.nt)) return false;
