@@ -369,8 +369,13 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
         } else {
             // intermediate: computed into registers, then written back in
             // place, (complemented,) clipped to the page with outside = 1
+            // items here are taken rows fastest (every lane's results stay in
+            // LDS): the 4-word groups of neighbouring lanes then start a row
+            // pitch apart instead of 32 bytes, which spreads the row pass's
+            // reads and the write-back over the banks
             uint64_t res[kItemsMax][WPT];
-            int r = tid / G, g = tid - (tid / G) * G;
+            const int dr2 = NT % NRo, dg2 = NT / NRo;
+            int r = tid % NRo, g = tid / NRo;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
                 if (tid + k * NT < items) {
@@ -384,13 +389,13 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
                         for (int i = 0; i < WPT; i++) res[k][i] = X[i + 1];
                     }
                 }
-                r += dr;
-                g += dg;
-                if (g >= G) { g -= G; r++; }
+                r += dr2;
+                g += dg2;
+                if (r >= NRo) { r -= NRo; g++; }
             }
             lds_barrier();
-            r = tid / G;
-            g = tid - (tid / G) * G;
+            r = tid % NRo;
+            g = tid / NRo;
             const uint64_t minv = P.mid_c ? kOnes : 0ull;
 #pragma unroll
             for (int k = 0; k < kItemsMax; k++) {
@@ -409,9 +414,9 @@ __device__ __forceinline__ bool process_tile(const RectPage &P, const Tile &T, u
                         }
                     }
                 }
-                r += dr;
-                g += dg;
-                if (g >= G) { g -= G; r++; }
+                r += dr2;
+                g += dg2;
+                if (r >= NRo) { r -= NRo; g++; }
             }
             lds_barrier();
             NRs = NRo;
