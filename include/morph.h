@@ -135,8 +135,8 @@ int morph_copy_async(void *dst, const void *src, size_t bytes, morph_stream_t st
  * ws may then be NULL).  One image of workspace is needed when the
  * operation runs as two launches: an element reaching more than 64 pixels
  * sideways or 128 rows down (split by the composition law), or an opening
- * or closing whose two stages bring more halo rows than a fused tile holds
- * output rows (51 x 51 on 2550-pixel rows, for instance).  Whether that
+ * or closing whose two stages bring more halo rows than 0.6 of the output
+ * rows a fused tile holds (51 x 51 on 2550-pixel rows, for instance).  Whether that
  * happens depends on the element and the width only, so the size queried
  * for a stack's total rows covers every page height.
  */
