@@ -229,8 +229,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
         const uint64_t sh = (a << 1) | up;
         uint64_t st = a & ~sh, en = ~a & sh;
         if (j > nw) { st = 0; en = 0; }
-        const int ns = __popcll(st), ne = __popcll(en);
-        const int is = wave_incl_scan(ns), ie = wave_incl_scan(ne);
+        const int ns = EMIT ? 0 : __popcll(st), ne = EMIT ? __popcll(en) : 0;
+        const int is = EMIT ? 0 : wave_incl_scan(ns), ie = EMIT ? wave_incl_scan(ne) : 0;
         if (EMIT) {
             // each run written whole by the lane of its end (see the
             // grouped kernel below)
@@ -245,12 +245,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void pack_to_rle_kernel(
             emit_word_runs(st, en, 64 * j, before, (int)(obase + cend + ie - ne), capi, runs);
             last_start = max(last_start, __shfl(incl, 63, 64));
         }
-        cstart += __shfl(is, 63, 64);
-        cend += __shfl(ie, 63, 64);
+        if (EMIT) cend += __shfl(ie, 63, 64); else cstart += __shfl(is, 63, 64);
         prev = (uint64_t)__shfl((int)(a >> 63), 63, 64);
     }
     if (!EMIT && lane == 0) counts[r] = cstart;
-    if (EMIT && trace && lane == 0) trace_add(trace, 0, (unsigned long long)cstart);
+    if (EMIT && trace && lane == 0) trace_add(trace, 0, (unsigned long long)cend);
 }
 
 // -------------------------------------------------------- runs -> packed
@@ -548,8 +547,10 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
         // blocks without a transition in all four rows of the wave (the
         // white space between text lines) change no row's state
         if (__builtin_amdgcn_ballot_w64((st | en) != 0) == 0) continue;
-        const int ns = __popcll(st), ne = __popcll(en);
-        const int is = group_incl_scan(ns), ie = group_incl_scan(ne);
+        // a row has as many ends as starts: the count pass scans the starts,
+        // the emit pass only the ends
+        const int ns = EMIT ? 0 : __popcll(st), ne = EMIT ? __popcll(en) : 0;
+        const int is = EMIT ? 0 : group_incl_scan(ns), ie = EMIT ? group_incl_scan(ne) : 0;
         if (EMIT) {
             // every run is written whole, as one pair, by the lane that holds
             // its end: its start is the nearest start bit below the end in
@@ -561,12 +562,11 @@ __global__ __launch_bounds__(256) void pack_to_rle_group_kernel(
             emit_word_runs(st, en, 64 * j, before, (int)(obase + cend + ie - ne), capi, runs);
             last_start = max(last_start, group_last(incl));
         }
-        cstart += group_last(is);
-        cend += group_last(ie);
+        if (EMIT) cend += group_last(ie); else cstart += group_last(is);
         prev = group_last(top);
     }
     if (!EMIT && gl == 0) counts[r] = cstart;
-    if (EMIT && trace && gl == 0) trace_add(trace, 0, (unsigned long long)cstart);
+    if (EMIT && trace && gl == 0) trace_add(trace, 0, (unsigned long long)cend);
 }
 
 // ---------------------------------------- packed -> runs of the transpose
