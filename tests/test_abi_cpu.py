@@ -67,6 +67,17 @@ def test_sizes():
     assert M.morph_rle_workspace_bytes("erode", 0, 3300, 1, (3, 3, 1, 1)) == 0
 
 
+def test_packed_openings_fused_or_split_on_letter_pages():
+    """On 2550-pixel rows an opening or closing fuses its two stages in one
+    tile (no workspace) while their halo rows stay within 0.6 of a fused
+    tile's rows: 3 x 3, 21 x 21, 31 x 1 and 1 x 31 fuse, 51 x 51 (100 halo
+    rows) takes two launches and one intermediate image."""
+    for op in ("open", "close"):
+        for se in [(3, 3, 1, 1), (21, 21, 10, 10), (1, 31, 0, 15), (31, 1, 15, 0)]:
+            assert M.morph_workspace_bytes(op, 0, 2550, 3300 * 256, se) == 0, (op, se)
+        assert M.morph_workspace_bytes(op, 0, 2550, 3300 * 256, (51, 51, 25, 25)) >= 40 * 3300 * 256 * 8
+
+
 class HostBuf:
     """Host memory standing in for device pointers in calls that must fail."""
 
